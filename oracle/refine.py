@@ -1,0 +1,148 @@
+"""Off-grid refinement of the direct decision (test infrastructure; see the package header).
+
+Not in the paper: the grid estimators stop at a grid cell.  The refinement
+maximises the exact direct decision D(theta) = sum_q |c_q(theta)|^2 (see
+direct.py) over continuous theta = (x, y, vx, vy) within one grid cell of a
+starting cell, by Newton ascent with analytic derivatives.
+
+Derivatives, for receiver q with legs d_1 = x - x_TX, d_2 = x - x_RX,q,
+rho_i = |d_i|, u_i = d_i / rho_i (eqs. (1)-(2)):
+  f_r = beta_r R,  beta_r = B/(c Ms);    f_d = beta_d <w, v>,  beta_d = f0 Tc / c
+  d f_r / d x = beta_r w,                 d f_d / d v = beta_d w
+  d f_d / d x = beta_d J v,               J = sum_i (I - u_i u_i^T) / rho_i
+  d2 f_r / dx dx = beta_r J,              d2 f_d / dx dv = beta_d J
+  d2 f_d / dx_a dx_b = -beta_d sum_i [u_b v_a + u_a v_b + (u.v)(delta_ab - 3 u_a u_b)] / rho_i^2
+With E = exp(-j 2 pi (f_r s + f_d m)) and the moments
+  M_pq = sum_{m,s} Y[m][s] E s^p m^q,
+  c = M_00,  dc/da = -j 2 pi (f_r,a M_10 + f_d,a M_01),
+  d2c/da db = -4 pi^2 (f_r,a f_r,b M_20 + (f_r,a f_d,b + f_d,a f_r,b) M_11 + f_d,a f_d,b M_02)
+              - j 2 pi (f_r,ab M_10 + f_d,ab M_01),
+  dD/da = 2 Re(conj(c) dc/da),  d2D/da db = 2 Re(conj(dc/db) dc/da + conj(c) d2c/da db).
+
+Iteration (coordinates z = (theta - theta_0) / h, h the grid steps; an axis
+with a single grid point is held fixed):
+  step  = sum_i (e_i . g) / max(|lambda_i|, 1e-12 max|lambda|) e_i over the
+          eigenpairs of the Hessian (the Newton step where the Hessian is
+          negative definite, an ascent step everywhere);
+  candidate = clamp(z + step, [-1, 1]); while D(candidate) < D(z), halve the
+          step (at most 30 times; no ascent -> stop);
+  stop when the accepted move is below `tol` cells or after `max_iter` steps.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import radar as rd
+
+ORDER = [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (0, 2)]   # (p, q) of the moments M_pq
+
+
+def moments(yq: np.ndarray, fr: float, fd: float) -> dict:
+    yq = np.asarray(yq).astype(np.complex128)
+    mc, ms = yq.shape
+    s = np.arange(ms, dtype=np.float64)[None, :]
+    m = np.arange(mc, dtype=np.float64)[:, None]
+    ye = yq * np.exp(-2j * np.pi * (fr * s + fd * m))
+    return {(p, q): complex(np.sum(ye * s ** p * m ** q)) for (p, q) in ORDER}
+
+
+def freq_derivs(radar: rd.Radar, q: int, theta):
+    """(f_r, f_d, grad f_r (4), grad f_d (4), hess f_r (4x4), hess f_d (4x4))."""
+    p = np.asarray(theta[:2], np.float64)
+    v = np.asarray(theta[2:], np.float64)
+    beta_r = radar.bw / (radar.c * radar.ms)
+    beta_d = radar.f0 * radar.tc / radar.c
+    w = np.zeros(2)
+    jac = np.zeros((2, 2))
+    hxx = np.zeros((2, 2))
+    rsum = 0.0
+    for anchor in (radar.tx, radar.rx[q]):
+        d = p - anchor
+        rho = float(np.hypot(d[0], d[1]))
+        if rho == 0.0:
+            continue
+        u = d / rho
+        rsum += rho
+        w += u
+        jac += (np.eye(2) - np.outer(u, u)) / rho
+        uv = float(u @ v)
+        hxx -= (np.outer(v, u) + np.outer(u, v) + uv * (np.eye(2) - 3.0 * np.outer(u, u))) / rho ** 2
+    fr = beta_r * rsum
+    fd = beta_d * float(w @ v)
+    gr = np.concatenate([beta_r * w, np.zeros(2)])
+    gd = np.concatenate([beta_d * (jac @ v), beta_d * w])
+    hr = np.zeros((4, 4))
+    hr[:2, :2] = beta_r * jac
+    hd = np.zeros((4, 4))
+    hd[:2, :2] = beta_d * hxx
+    hd[:2, 2:] = beta_d * jac
+    hd[2:, :2] = beta_d * jac.T
+    return fr, fd, gr, gd, hr, hd
+
+
+def decision_derivs(y: np.ndarray, radar: rd.Radar, theta):
+    """(D, gradient (4), Hessian (4x4)) of the direct decision at theta."""
+    dval = 0.0
+    grad = np.zeros(4)
+    hess = np.zeros((4, 4))
+    tp = 2.0 * np.pi
+    for q in range(radar.k):
+        fr, fd, gr, gd, hr, hd = freq_derivs(radar, q, theta)
+        mo = moments(y[q], fr, fd)
+        c = mo[(0, 0)]
+        dc = -1j * tp * (gr * mo[(1, 0)] + gd * mo[(0, 1)])
+        d2c = (-tp * tp * (np.outer(gr, gr) * mo[(2, 0)] + (np.outer(gr, gd) + np.outer(gd, gr)) * mo[(1, 1)]
+                           + np.outer(gd, gd) * mo[(0, 2)])
+               - 1j * tp * (hr * mo[(1, 0)] + hd * mo[(0, 1)]))
+        dval += abs(c) ** 2
+        grad += 2.0 * np.real(np.conj(c) * dc)
+        hess += 2.0 * np.real(np.outer(dc, np.conj(dc)) + np.conj(c) * d2c)
+    return dval, grad, hess
+
+
+def decision_value(y, radar, theta) -> float:
+    total = 0.0
+    for q in range(radar.k):
+        fr, fd, *_ = freq_derivs(radar, q, theta)
+        total += abs(moments(y[q], fr, fd)[(0, 0)]) ** 2
+    return total
+
+
+def grid_steps(grid) -> np.ndarray:
+    return np.array([0.0 if grid.n[a] == 1 else (grid.hi[a] - grid.lo[a]) / (grid.n[a] - 1) for a in range(4)])
+
+
+def refine_one(y, radar: rd.Radar, theta0, h, max_iter: int = 20, tol: float = 1e-7):
+    theta0 = np.asarray(theta0, np.float64)
+    z = np.zeros(4)
+    free = h > 0
+    d_cur = decision_value(y, radar, theta0)
+    for _ in range(max_iter):
+        _, g, hth = decision_derivs(y, radar, theta0 + z * h)
+        gz = np.where(free, g * h, 0.0)
+        hz = hth * np.outer(h, h)
+        lam, vec = np.linalg.eigh(hz)
+        floor = 1e-12 * max(np.max(np.abs(lam)), 1e-300)
+        step = vec @ ((vec.T @ gz) / np.maximum(np.abs(lam), floor))
+        step = np.where(free, step, 0.0)
+        accepted = False
+        for _ in range(31):
+            cand = np.clip(z + step, -1.0, 1.0)
+            d_new = decision_value(y, radar, theta0 + cand * h)
+            if d_new >= d_cur:
+                accepted = True
+                break
+            step = step * 0.5
+        if not accepted:
+            break
+        move = float(np.max(np.abs(cand - z)))
+        z, d_cur = cand, d_new
+        if move < tol:
+            break
+    return theta0 + z * h
+
+
+def refine(y, radar: rd.Radar, grid, cells, max_iter: int = 20, tol: float = 1e-7) -> np.ndarray:
+    """Refined (x, y, vx, vy) for each starting cell (linear grid index)."""
+    h = grid_steps(grid)
+    return np.stack([refine_one(y, radar, rd.grid_point(grid, int(c)), h, max_iter, tol) for c in cells])
