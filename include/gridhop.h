@@ -1,0 +1,187 @@
+/*
+ * gridhop.h - C ABI of the MI355X (gfx950) grid-hopping library.
+ *
+ * Grid hopping (Monnoyer et al., "Grid Hopping: Accelerating Direct
+ * Estimation Algorithms for Multistatic FMCW Radar") evaluates the direct
+ * estimator's decision function over a 4D location-velocity grid
+ * (x, y, vx, vy) by interpolating each receiver's 2D range-Doppler FFT map
+ * instead of computing the scalar products with the model atoms.
+ *
+ * Conventions shared by every entry point
+ *  - Device pointers (prefix d_) are caller-owned HIP device allocations; the
+ *    library never retains a pointer after returning and never allocates
+ *    device memory: scratch space comes from caller workspaces whose size the
+ *    *_workspace_bytes() queries give.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Every call only enqueues work; results are valid once the caller has
+ *    synchronised the stream, and device faults surface there.
+ *  - Arguments are validated on the host before anything is enqueued.  On
+ *    error nothing is enqueued, a negative gh_status is returned and
+ *    gh_last_error() describes the failure.  No C++ exception crosses the ABI.
+ *  - Complex numbers are interleaved (re, im) pairs of float (complex64) or
+ *    double.
+ *  - Frames: d_y is complex64 [n_rx][n_chirps][n_samples], sample index
+ *    fastest: row m of receiver q is chirp m of Y_q in C^{Mc x Ms}
+ *    (paper Sec. II, eq. (3)).
+ *  - Maps: complex64 [n_rx][N_r][N_d], N_r = pad_range * n_samples range bins,
+ *    N_d = pad_doppler * n_chirps Doppler bins, Doppler index fastest.
+ *  - Grids: axes (x, y, vx, vy) in metres and metres/second; point i of axis a
+ *    is lo[a] + i * (hi[a] - lo[a]) / (n[a] - 1) (n[a] == 1: lo[a]).  The
+ *    linear index of (ix, iy, ivx, ivy) is ((ix*Ny + iy)*Nvx + ivx)*Nvy + ivy;
+ *    decision volumes are float [Nx][Ny][Nvx][Nvy] in that order.  A "block"
+ *    is one location's Nvx*Nvy velocity slab.
+ *  - Sensing (paper Sec. II, eqs. (1)-(2), physical FMCW scaling): for
+ *    receiver q, R_q = |x - tx| + |x - rx_q|, U_q = <unit(x - tx) +
+ *    unit(x - rx_q), v>; cycles per sample f_r = B R_q / (c Ms), cycles per
+ *    chirp f_d = f0 Tc U_q / c; map coordinates t_r = f_r N_r, t_d = f_d N_d.
+ */
+#ifndef GRIDHOP_H
+#define GRIDHOP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GH_ABI_VERSION 1
+#define GH_MAX_RX 16
+#define GH_MAX_SUPPORT 32
+
+typedef enum {
+    GH_OK = 0,
+    GH_EINVAL = -1,        /* invalid argument (NULL pointer, bad size, non-finite parameter) */
+    GH_EUNSUPPORTED = -2,  /* valid request outside what this build implements */
+    GH_EHIP = -3,          /* a HIP runtime call failed (no device, launch failure) */
+    GH_EWORKSPACE = -4     /* caller workspace smaller than the matching *_workspace_bytes() */
+} gh_status;
+
+typedef enum { GH_INTERP_BILINEAR = 0, GH_INTERP_BICUBIC = 1 } gh_interp;
+
+typedef enum { GH_GEMM_F32 = 0, GH_GEMM_BF16 = 1 } gh_gemm_dtype;
+
+/* Radar and frame description (paper Sec. II).  Limits: n_samples and
+ * n_chirps powers of two in [8, 1024]; pad_range, pad_doppler in {1, 2, 4, 8};
+ * N_r and N_d at most 4096; 1 <= n_rx <= GH_MAX_RX; positive finite f0, B,
+ * Tc, c.  `centered` selects maps of the centred atoms (index s - (Ms-1)/2,
+ * m - (Mc-1)/2), whose interpolation kernel is real; 0 gives plain DFT maps.
+ * `rx` is a HOST pointer to n_rx (x, y) pairs in metres, read during the call. */
+typedef struct {
+    double f0_hz;
+    double bandwidth_hz;
+    double t_chirp_s;
+    double c_mps;
+    int32_t n_samples;     /* Ms */
+    int32_t n_chirps;      /* Mc */
+    int32_t pad_range;     /* P along fast time */
+    int32_t pad_doppler;   /* P along slow time */
+    int32_t n_rx;          /* K (the paper's Q) */
+    int32_t centered;
+    double tx[2];
+    const double *rx;
+} gh_radar;
+
+/* Inclusive 4D grid (paper Sec. III: X_G x V_G).  n[a] >= 1, lo[a] <= hi[a],
+ * total points below 2^31. */
+typedef struct {
+    double lo[4];
+    double hi[4];
+    int32_t n[4];
+} gh_grid;
+
+/* A decision maximum: value and linear grid index (ties -> lowest index). */
+typedef struct {
+    float value;
+    int32_t reserved;
+    int64_t index;
+} gh_peak;
+
+/* ABI version of the loaded library (GH_ABI_VERSION at build time). */
+int gh_abi_version(void);
+
+/* Message of the last failed call on this thread ("" after success).  The
+ * pointer stays valid until the next gh_* call on the same thread. */
+const char *gh_last_error(void);
+
+/* Range-Doppler maps (paper Sec. III, first step of the indirect method, and
+ * Sec. IV, the FFT outputs z that grid hopping interpolates):
+ *   Z_q[i][l] = sum_{m<Mc} sum_{s<Ms} Y_q[m][s]
+ *               exp(-j 2 pi (i (s - c_s) / N_r + l (m - c_m) / N_d)),
+ * c_s = (Ms-1)/2, c_m = (Mc-1)/2 if radar->centered, else 0: the zero-padded
+ * (zeros appended, rectangular window) forward 2D DFT.
+ * d_y: complex64 [K][Mc][Ms] (read only).  d_maps: complex64 [K][N_r][N_d]
+ * (written; must not overlap d_y).  FP32 arithmetic. */
+int gh_rd_maps(const gh_radar *radar, const void *d_y, void *d_maps, void *stream);
+
+/* Grid-hopping decision (paper Sec. IV, eq. (7)): for every grid point and
+ * receiver q, interpolate map q at (t_r, t_d) (bilinear: 2x2 taps; bicubic:
+ * 4x4 Keys taps, a = -1/2; periodic in both map axes, with the sign
+ * (-1)^(M-1) per period for centred maps) and sum |.|^2 over receivers:
+ *   D_gh(x, v) = sum_q |I(Z_q; t_r, t_d)|^2.
+ * d_maps: output of gh_rd_maps for the same radar.
+ * d_decision: float volume (NULL: not written, argmax only).
+ * d_block: gh_peak [Nx*Ny], per-location maxima (required).
+ * d_argmax: gh_peak [1], global maximum (NULL: not computed).
+ * FP32 interpolation and accumulation; geometry in FP64, Doppler coordinate
+ * in 32-bit fixed point (exact wrap). */
+int gh_decision(const gh_radar *radar, const gh_grid *grid, const void *d_maps, int32_t interp,
+                float *d_decision, gh_peak *d_block, gh_peak *d_argmax, void *stream);
+
+/* Workspace of gh_direct_decision in bytes. */
+size_t gh_direct_workspace_bytes(const gh_radar *radar, const gh_grid *grid, int32_t gemm_dtype);
+
+/* Direct decision (paper Sec. I and III; the scalar products of eq. (3)'s
+ * atoms with the frames, evaluated exactly):
+ *   D_dir(x, v) = sum_q | sum_{m,s} Y_q[m][s] exp(-j 2 pi (f_r s + f_d m)) |^2
+ * as two contractions per receiver: G_q[x][m] = sum_s Y_q[m][s] conj(a_s(f_r))
+ * (range zoom over locations), then per location the Doppler zoom
+ * sum_m G_q[x][m] conj(b_m(f_d)) over the velocity slab.  gemm_dtype selects
+ * FP32 or BF16 operands (FP32 accumulation either way).
+ * d_y: complex64 frames.  d_ws: workspace of gh_direct_workspace_bytes().
+ * Outputs as gh_decision. */
+int gh_direct_decision(const gh_radar *radar, const gh_grid *grid, const void *d_y, int32_t gemm_dtype,
+                       void *d_ws, size_t ws_bytes, float *d_decision, gh_peak *d_block,
+                       gh_peak *d_argmax, void *stream);
+
+/* Workspace of gh_bomp_step in bytes. */
+size_t gh_bomp_workspace_bytes(const gh_radar *radar, const gh_grid *grid, int32_t use_direct,
+                               int32_t gemm_dtype);
+
+/* One Block-OMP iteration (multi-target extension the paper names as future
+ * work, Sec. VI):
+ *   1. decision on the residual d_resid (grid hopping on gh_rd_maps(d_resid),
+ *      written to d_maps, if use_direct == 0; else the direct decision);
+ *   2. select the maximum over the grid excluding the n_support cells already
+ *      in d_support; store its index at d_support[n_support];
+ *   3. for each receiver, least squares over the n_support + 1 selected cells
+ *      with the exact atoms A_q(theta) = b(f_d) (x) a(f_r) of eq. (3):
+ *      normal equations in FP64 with the Gram matrix in closed form;
+ *      alpha (complex64 [n_support+1][K], row t = cell d_support[t]) to d_alpha;
+ *   4. d_resid <- Y - sum_t alpha_t A(theta_t) (FP32).
+ * d_y: original frames (read).  d_resid: complex64 [K][Mc][Ms], in/out (the
+ * caller starts with a copy of d_y).  d_maps: complex64 map buffer (written
+ * when use_direct == 0; may be NULL otherwise).  d_support: int64
+ * [max_support], in/out.  0 <= n_support < max_support <= GH_MAX_SUPPORT.
+ * d_selected: gh_peak [1] (NULL: not written), the selected maximum.
+ * Everything stays on the device; no host synchronisation inside. */
+int gh_bomp_step(const gh_radar *radar, const gh_grid *grid, const void *d_y, void *d_resid, void *d_maps,
+                 int32_t use_direct, int32_t interp, int32_t gemm_dtype, int64_t *d_support,
+                 int32_t n_support, int32_t max_support, void *d_alpha, gh_peak *d_selected,
+                 void *d_ws, size_t ws_bytes, void *stream);
+
+/* Off-grid refinement of the direct decision (not in the paper): starting at
+ * each cell (int64 linear grid index, device), maximise D_dir over continuous
+ * (x, y, vx, vy) within one grid step per axis by Newton ascent with analytic
+ * gradient and Hessian (eigenvalues replaced by -|lambda|, step halving until
+ * the decision does not decrease, clamping to the box).  Stops when the move
+ * is below 1e-7 grid steps or after max_iter (1..100) iterations.
+ * d_theta: double [n_cells][4] out.  FP64 accumulation, fixed-point phases. */
+int gh_refine(const gh_radar *radar, const gh_grid *grid, const void *d_y, const int64_t *d_cells,
+              int32_t n_cells, int32_t max_iter, double *d_theta, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRIDHOP_H */

@@ -1,0 +1,169 @@
+// Internal declarations of the gfx950 grid-hopping library: kernel parameter
+// blocks (passed by value), device helpers and the host launchers that the
+// C ABI layer (abi.hip) dispatches to.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gridhop.h"
+
+namespace gh {
+
+constexpr int kMaxRx = GH_MAX_RX;
+constexpr int kMaxSupport = GH_MAX_SUPPORT;
+
+// Radar constants in the form the kernels use.  Sensing functions (paper
+// Sec. II, eqs. (1)-(2)) with the FMCW scaling: continuous map coordinates
+// t_r = kr * R (range bins) and t_d = kd * U (Doppler bins); f_r = fr_per_m * R
+// cycles per sample and f_d = fd_per_mps * U cycles per chirp.
+struct Geom {
+    double tx[2];
+    double rx[kMaxRx][2];
+    double kr;          // B * P_r / c
+    double kd;          // f0 * Tc * P_d * Mc / c
+    double fr_per_m;    // B / (c * Ms)
+    double fd_per_mps;  // f0 * Tc / c
+    int k, ms, mc, nr, nd, pr, pd;
+    int log2_ms, log2_mc, log2_nr, log2_nd;
+    int centered;
+    float sign_r, sign_d;  // factor per period of the (centred) correlation: (-1)^(M-1) or 1
+};
+
+struct GridP {
+    double lo[4];
+    double step[4];
+    int n[4];
+    int nloc;   // n[0] * n[1]
+    int nv;     // n[2] * n[3]
+};
+
+// ---- small device helpers -------------------------------------------------
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// exp(-j 2 pi u) for a phase u = ph * 2^-32 cycles held in 32-bit fixed point
+// (the wrap modulo one cycle is exact integer overflow).
+__device__ __forceinline__ float2 expm_fixed(uint32_t ph) {
+    float s, c;
+    // sin/cos of pi * x with x = 2 * ph * 2^-32 in [0, 2)
+    sincospif(__uint2float_rn(ph) * 4.656612873077393e-10f, &s, &c);
+    return make_float2(c, -s);
+}
+
+// Round a phase in cycles (any sign or size) to 32-bit fixed point, modulo 1 cycle.
+__host__ __device__ __forceinline__ uint32_t cycles_to_fixed(double cyc) {
+    double f = cyc - floor(cyc);                   // [0, 1)
+    double scaled = f * 4294967296.0;
+    unsigned long long r = (unsigned long long)(scaled + 0.5);
+    return (uint32_t)(r & 0xffffffffull);
+}
+
+// Signed increment in cycles to a 32-bit two's complement fixed-point step.
+__host__ __device__ __forceinline__ uint32_t cycles_to_fixed_step(double cyc) {
+    return cycles_to_fixed(cyc);  // modular arithmetic: the step is also taken mod 1 cycle
+}
+
+// Bistatic geometry of one location and receiver, FP64.
+__device__ __forceinline__ void bistatic(const Geom& g, int q, double x, double y, double& r, double& wx,
+                                         double& wy) {
+    double dx0 = x - g.tx[0], dy0 = y - g.tx[1];
+    double dx1 = x - g.rx[q][0], dy1 = y - g.rx[q][1];
+    double n0 = sqrt(dx0 * dx0 + dy0 * dy0);
+    double n1 = sqrt(dx1 * dx1 + dy1 * dy1);
+    r = n0 + n1;
+    wx = 0.0;
+    wy = 0.0;
+    if (n0 > 0.0) { wx += dx0 / n0; wy += dy0 / n0; }
+    if (n1 > 0.0) { wx += dx1 / n1; wy += dy1 / n1; }
+}
+
+// (value, index) max with ties to the lowest index.
+__device__ __forceinline__ void peak_merge(float& v, int& i, float v2, int i2) {
+    if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
+}
+
+__device__ __forceinline__ void wave_peak(float& v, int& i) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        float v2 = __shfl_xor(v, off, 64);
+        int i2 = __shfl_xor(i, off, 64);
+        peak_merge(v, i, v2, i2);
+    }
+}
+
+// Per-location epilogue shared by the decision kernels: write the slab (if
+// `dec`), reduce its maximum (ties -> lowest index) skipping excluded cells,
+// and store the block peak.  `acc[j]` holds the value of point tid + j*NT.
+template <int NT, int NPTS>
+__device__ __forceinline__ void slab_epilogue(const float (&acc)[NPTS], int nv, int loc, float* __restrict__ dec,
+                                              gh_peak* __restrict__ block, const int* excl_local, int nex,
+                                              float* red_v, int* red_i) {
+    const int tid = threadIdx.x;
+    float best_v = -INFINITY;
+    int best_i = 0x7fffffff;
+#pragma unroll
+    for (int j = 0; j < NPTS; ++j) {
+        const int v = tid + j * NT;
+        if (v < nv) {
+            if (dec) dec[(size_t)loc * nv + v] = acc[j];
+            bool skip = false;
+            for (int e = 0; e < nex; ++e) skip |= (excl_local[e] == v);
+            if (!skip) peak_merge(best_v, best_i, acc[j], v);
+        }
+    }
+    wave_peak(best_v, best_i);
+    const int wid = tid >> 6;
+    if ((tid & 63) == 0) {
+        red_v[wid] = best_v;
+        red_i[wid] = best_i;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < NT / 64; ++w) peak_merge(best_v, best_i, red_v[w], red_i[w]);
+        gh_peak p;
+        p.value = best_v;
+        p.reserved = 0;
+        p.index = (int64_t)loc * nv + (best_i == 0x7fffffff ? 0 : best_i);
+        block[loc] = p;
+    }
+}
+
+// Exclusion list entries that fall in this location's slab (thread 0 only).
+__device__ __forceinline__ int local_exclusions(const int64_t* excl, int nexcl, int loc, int nv, int* out) {
+    int n = 0;
+    const int64_t base = (int64_t)loc * nv;
+    for (int e = 0; e < nexcl; ++e) {
+        const int64_t d = excl[e] - base;
+        if (d >= 0 && d < nv) out[n++] = (int)d;
+    }
+    return n;
+}
+
+// ---- host launchers (return hipError_t of the launches) --------------------
+
+hipError_t launch_rd_maps(const Geom& g, const float2* y, float2* maps, hipStream_t st);
+
+hipError_t launch_gh_sweep(const Geom& g, const GridP& gp, const float2* maps, int interp, float* dec,
+                           gh_peak* block, const int64_t* excl, int nexcl, hipStream_t st);
+
+hipError_t launch_peak_final(const gh_peak* block, int nblock, gh_peak* out, int64_t* support_slot,
+                             hipStream_t st);
+
+size_t direct_ws_bytes(const Geom& g, const GridP& gp, int gemm);
+hipError_t launch_direct(const Geom& g, const GridP& gp, const float2* y, int gemm, void* ws, float* dec,
+                         gh_peak* block, const int64_t* excl, int nexcl, hipStream_t st);
+
+size_t bomp_fit_ws_bytes(const Geom& g);
+hipError_t launch_bomp_fit(const Geom& g, const GridP& gp, const float2* y, float2* resid,
+                           const int64_t* support, int nsel, float2* alpha, void* ws, hipStream_t st);
+
+hipError_t launch_refine(const Geom& g, const GridP& gp, const float2* y, const int64_t* cells, int ncells,
+                         int max_iter, double* theta, hipStream_t st);
+
+}  // namespace gh

@@ -1,0 +1,121 @@
+"""Host-side tests of the C ABI: the built library loads, exports every declared
+entry point, and rejects invalid arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2307_16550_amd import gridhop as gh
+from paper_2307_16550_amd import scene as sc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "gridhop.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gh_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(gh.LIB_PATH):
+        pytest.fail("libgridhop.so is not built (python -m paper_2307_16550_amd.build)")
+    return gh.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert set(names) == set(gh.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_abi_version(lib):
+    assert lib.gh_abi_version() == 1
+
+
+def radar(**kw):
+    s = sc.make_scene(1, 0)
+    r = gh.Radar.from_scene(s)
+    for k, v in kw.items():
+        setattr(r.c_struct, k, v)
+    return r
+
+
+GRID = gh.make_grid((5, -10, -10, -10), (25, 10, 10, 10), (32, 32, 8, 8))
+FAKE = ctypes.c_void_p(0x1000)     # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n_samples", 48), ("n_samples", 4), ("n_chirps", 2048), ("pad_range", 3), ("pad_doppler", 16),
+    ("n_rx", 0), ("n_rx", 17), ("centered", 2), ("f0_hz", -1.0), ("bandwidth_hz", float("nan")),
+    ("c_mps", 0.0), ("t_chirp_s", float("inf")),
+])
+def test_invalid_radar_rejected(lib, field, value):
+    r = radar(**{field: value})
+    rc = lib.gh_rd_maps(ctypes.byref(r.c_struct), FAKE, ctypes.c_void_p(0x100000000), None)
+    assert rc == gh.GH_EINVAL
+    assert gh.last_error()
+
+
+def test_null_and_overlap_rejected(lib):
+    r = radar()
+    assert lib.gh_rd_maps(None, FAKE, FAKE, None) == gh.GH_EINVAL
+    assert lib.gh_rd_maps(ctypes.byref(r.c_struct), None, FAKE, None) == gh.GH_EINVAL
+    assert lib.gh_rd_maps(ctypes.byref(r.c_struct), FAKE, FAKE, None) == gh.GH_EINVAL
+    assert "overlap" in gh.last_error()
+    r.c_struct.rx = None
+    assert lib.gh_rd_maps(ctypes.byref(r.c_struct), FAKE, ctypes.c_void_p(0x100000000), None) == gh.GH_EINVAL
+
+
+@pytest.mark.parametrize("lo,hi,n", [
+    ((5, -10, -10, -10), (25, 10, 10, 10), (0, 32, 8, 8)),
+    ((25, -10, -10, -10), (5, 10, 10, 10), (32, 32, 8, 8)),
+    ((5, -10, -10, -10), (25, 10, 10, 10), (32, 32, 128, 64)),     # slab above 4096
+    ((5, -10, -10, float("nan")), (25, 10, 10, 10), (32, 32, 8, 8)),
+])
+def test_invalid_grid_rejected(lib, lo, hi, n):
+    r = radar()
+    g = gh.make_grid(lo, hi, n)
+    rc = lib.gh_decision(ctypes.byref(r.c_struct), ctypes.byref(g), FAKE, 0, None, FAKE, None, None)
+    assert rc in (gh.GH_EINVAL, gh.GH_EUNSUPPORTED)
+
+
+def test_decision_argument_checks(lib):
+    r = radar()
+    assert lib.gh_decision(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, 7, None, FAKE, None, None) == gh.GH_EINVAL
+    assert lib.gh_decision(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, 0, None, None, None, None) == gh.GH_EINVAL
+
+
+def test_workspace_queries_and_shortfall(lib):
+    r = radar()
+    need = lib.gh_direct_workspace_bytes(ctypes.byref(r.c_struct), ctypes.byref(GRID), 0)
+    assert need >= 3 * 32 * 32 * 32 * 8
+    rc = lib.gh_direct_decision(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, 0, FAKE, need - 1, None, FAKE,
+                                None, None)
+    assert rc == gh.GH_EWORKSPACE
+    assert lib.gh_direct_workspace_bytes(ctypes.byref(r.c_struct), ctypes.byref(GRID), 9) == 0
+    nb = lib.gh_bomp_workspace_bytes(ctypes.byref(r.c_struct), ctypes.byref(GRID), 0, 0)
+    assert nb >= 32 * 32 * 16
+
+
+def test_bomp_and_refine_argument_checks(lib):
+    r = radar()
+    ws = lib.gh_bomp_workspace_bytes(ctypes.byref(r.c_struct), ctypes.byref(GRID), 0, 0)
+    args = [ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, ctypes.c_void_p(0x200000000), FAKE, 0, 0, 0, FAKE]
+    assert lib.gh_bomp_step(*args, 3, 3, FAKE, None, FAKE, ws, None) == gh.GH_EINVAL      # n_support == max
+    assert lib.gh_bomp_step(*args, 0, 33, FAKE, None, FAKE, ws, None) == gh.GH_EINVAL     # max above limit
+    assert lib.gh_bomp_step(*args, 0, 3, FAKE, None, FAKE, ws - 1, None) == gh.GH_EWORKSPACE
+    assert lib.gh_refine(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, FAKE, 1, 0, FAKE, None) == gh.GH_EINVAL
+    assert lib.gh_refine(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, FAKE, 0, 20, FAKE, None) == gh.GH_OK
+
+
+def test_error_message_cleared_after_success(lib):
+    r = radar()
+    lib.gh_rd_maps(None, FAKE, FAKE, None)
+    assert gh.last_error()
+    assert lib.gh_refine(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, FAKE, 0, 20, FAKE, None) == gh.GH_OK
+    assert gh.last_error() == ""
