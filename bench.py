@@ -1,0 +1,294 @@
+#!/usr/bin/env python3
+"""Benchmark of the grid-hopping hot path on one MI355X.
+
+One step is one synthetic frame of the paper-scale workload (4 receivers,
+Ms = 256 samples x Mc = 128 chirps, complex64, 3 targets, SNR 10 dB, f0 = 24 GHz,
+B = 250 MHz, Tc = 256 us) through every row of the hot path, all enqueued on
+one stream with no host synchronisation inside the step:
+  1. range-Doppler maps (zero padding x4): 4 maps of 1024 x 512 bins;
+  2. grid-hopping decision, bilinear, on the 128 x 128 x 32 x 32 grid
+     (16,777,216 points), FP32 volume written, block maxima, global argmax;
+  3. direct decision on the stride-2 64 x 64 x 16 x 16 subgrid (1,048,576
+     points), volume written, block maxima, global argmax;
+  4. Block-OMP, 3 iterations (each: maps of the residual, grid-hopping
+     argmax-only sweep with the support excluded, least-squares fit, residual);
+  5. Newton refinement of the 3 selected cells.
+Grid points evaluated per step: 4 x 16,777,216 (grid hopping) + 1,048,576
+(direct).  `value` is that count divided by the measured step time.
+
+The roofline object covers the dominant kernel, the grid-hopping sweep of
+step 2, timed with HIP events on the stream it runs on; its algorithmic bytes
+per launch are the FP32 volume write, one read of the four maps and the block
+maxima.  The CPU baseline runs the FP64 numpy oracle in a child process on a
+bounded sample of the same frame, one thread, and scales its per-point rates
+to the step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import tempfile
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+CFG = 2
+HBM_PEAK_GBS = 8000.0
+BOMP_ITERS = 3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--interp", choices=["bilinear", "bicubic"], default="bilinear")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device copy of this size (HBM counter calibration) and exit")
+    ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
+    return ap.parse_args()
+
+
+# ----------------------------------------------------------------------------- CPU baseline (oracle)
+
+def cpu_worker(path):
+    """Child process: time the FP64 oracle on a bounded sample; compare with the GPU samples."""
+    import numpy as np
+
+    from oracle import bomp as obomp, direct as odirect, gh as ogh, maps as omaps
+    from oracle import radar as ordr, refine as orefine
+    from paper_2307_16550_amd import scene as sc
+
+    job = np.load(path, allow_pickle=False)
+    s = sc.make_scene(CFG, 0)
+    r = ordr.radar_from_scene(s)
+    grid = s.grid
+    dgrid = sc.direct_grid(s, CFG)
+    interp = int(job["interp"])
+    t0 = time.perf_counter()
+    z = omaps.rd_maps(s.y, r.pad_r, r.pad_d, r.centered)
+    t_maps = time.perf_counter() - t0
+
+    def points(g, idx):
+        ax = ordr.grid_axes(g)
+        n = g.n
+        return (ax[0][idx // (n[1] * n[2] * n[3])], ax[1][(idx // (n[2] * n[3])) % n[1]],
+                ax[2][(idx // n[3]) % n[2]], ax[3][idx % n[3]])
+
+    gh_idx = job["gh_idx"]
+    pts = points(grid, gh_idx)
+    t0 = time.perf_counter()
+    gh_ref = ogh.gh_points(z, r, *pts, interp)
+    t_gh_pt = (time.perf_counter() - t0) / len(gh_idx)
+
+    d_idx = job["dir_idx"]
+    dpts = points(dgrid, d_idx)
+    t0 = time.perf_counter()
+    dir_ref = odirect.direct_points(s.y, r, *dpts)
+    t_dir_pt = (time.perf_counter() - t0) / len(d_idx)
+
+    support = [int(c) for c in job["support"]]
+    t0 = time.perf_counter()
+    for t in range(1, len(support) + 1):
+        obomp.fit(s.y, r, grid, support[:t])
+    t_fit = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    orefine.refine(s.y, r, grid, support[:1])
+    t_ref1 = time.perf_counter() - t0
+
+    n_gh, n_dir = grid.size, dgrid.size
+    t_step = (1 + BOMP_ITERS) * (t_maps + n_gh * t_gh_pt) + n_dir * t_dir_pt + t_fit + len(support) * t_ref1
+    sampled = t_maps + len(gh_idx) * t_gh_pt + len(d_idx) * t_dir_pt + t_fit + t_ref1
+    gh_scale = max(float(np.max(gh_ref)), float(job["gh_max"]))
+    dir_scale = max(float(np.max(dir_ref)), float(job["dir_max"]))
+    out = {
+        "value": ((1 + BOMP_ITERS) * n_gh + n_dir) / t_step,
+        "unit": "grid points/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"FP64 numpy oracle, 1 thread: maps of the frame, grid hopping at {len(gh_idx)} points, "
+                   f"direct at {len(d_idx)} points, BOMP fits for supports of 1..{len(support)}, one refinement; "
+                   f"per-point and per-call times scaled to the step ({sampled:.1f} s of CPU work measured)"),
+        "step_seconds_estimate": t_step,
+        "gh_points_per_s": 1.0 / t_gh_pt,
+        "direct_points_per_s": 1.0 / t_dir_pt,
+        "max_rel_error_gh": float(np.max(np.abs(job["gh_gpu"] - gh_ref)) / gh_scale),
+        "max_rel_error_direct": float(np.max(np.abs(job["dir_gpu"] - dir_ref)) / dir_scale),
+    }
+    print(json.dumps(out))
+
+
+def cpu_baseline(job):
+    import numpy as np
+    fd, path = tempfile.mkstemp(suffix=".npz")
+    os.close(fd)
+    try:
+        np.savez(path, **job)
+        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+                   HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+        res = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-worker", path],
+                             capture_output=True, text=True, env=env, timeout=600)
+        if res.returncode != 0:
+            return {"error": res.stderr[-2000:]}
+        return json.loads(res.stdout.strip().splitlines()[-1])
+    finally:
+        os.unlink(path)
+
+
+# ----------------------------------------------------------------------------- GPU benchmark
+
+def main():
+    args = parse()
+    if args.cpu_worker:
+        cpu_worker(args.cpu_worker)
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the frame path shards by frames across GPUs, which this benchmark does not run)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2307_16550_amd import gridhop as gh
+    from paper_2307_16550_amd import scene as sc
+
+    dev = torch.device("cuda:0")
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.copy_calibration_mib, "launches": 3}))
+        return 0
+
+    interp = gh.BICUBIC if args.interp == "bicubic" else gh.BILINEAR
+    s = sc.make_scene(CFG, 0)
+    radar = gh.Radar.from_scene(s)
+    grid = gh.grid_of(s.grid)
+    dgrid_s = sc.direct_grid(s, CFG)
+    dgrid = gh.grid_of(dgrid_s)
+    y = torch.from_numpy(s.y).to(dev)
+    maps = torch.empty((radar.k, radar.nr, radar.nd), dtype=torch.complex64, device=dev)
+    n_gh, n_dir = s.grid.size, dgrid_s.size
+    nloc, nloc_d = s.grid.n[0] * s.grid.n[1], dgrid_s.n[0] * dgrid_s.n[1]
+    dec = torch.empty(tuple(s.grid.n), dtype=torch.float32, device=dev)
+    block = gh.peaks_tensor(nloc, dev)
+    arg = gh.peaks_tensor(1, dev)
+    ws = torch.empty(gh.direct_workspace_bytes(radar, dgrid), dtype=torch.uint8, device=dev)
+    ddec = torch.empty(tuple(dgrid_s.n), dtype=torch.float32, device=dev)
+    dblock = gh.peaks_tensor(nloc_d, dev)
+    darg = gh.peaks_tensor(1, dev)
+    bomp = gh.BompState(radar, grid, y, max_support=BOMP_ITERS, use_direct=False, interp=interp)
+    theta = torch.empty((BOMP_ITERS, 4), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    marks = []
+
+    def step(record):
+        e = [ev() for _ in range(6)] if record else None
+        if record:
+            e[0].record(stream)
+        gh.rd_maps(radar, y, maps)
+        if record:
+            e[1].record(stream)
+        gh.decision(radar, grid, maps, interp, dec=dec, block=block, want_argmax=False)
+        if record:
+            e[2].record(stream)
+        gh.argmax(block, arg)
+        if record:
+            e[3].record(stream)
+        gh.direct_decision(radar, dgrid, y, ws=ws, dec=ddec, block=dblock, want_argmax=False)
+        if record:
+            e[4].record(stream)
+        gh.argmax(dblock, darg)
+        bomp.reset()
+        for _ in range(BOMP_ITERS):
+            bomp.step()
+        gh.refine(radar, grid, y, bomp.support, theta=theta)
+        if record:
+            e[5].record(stream)
+            marks.append(e)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    def avg(i, j):
+        return float(np.mean([m[i].elapsed_time(m[j]) for m in marks])) * 1e-3
+
+    t_maps, t_sweep, t_arg, t_dir, t_total = avg(0, 1), avg(1, 2), avg(2, 3), avg(3, 4), avg(0, 5)
+    ms_step = wall / args.steps * 1e3
+    pts_step = (1 + BOMP_ITERS) * n_gh + n_dir
+    sweep_bytes = 4 * n_gh + radar.k * radar.nr * radar.nd * 8 + 16 * nloc
+    achieved = sweep_bytes / t_sweep / 1e9
+
+    line = {
+        "metric": "4D grid points/s, grid hopping vs direct on 1 MI355X at stated error",
+        "value": pts_step / (ms_step * 1e-3),
+        "unit": "grid points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"paper-scale frame: K=4 RX, Ms=256 x Mc=128 complex64, 3 targets, SNR 10 dB, pad x4; "
+                         f"grid hopping ({args.interp}) on 128x128x32x32, direct (FP32) on the 64x64x16x16 subgrid, "
+                         f"Block-OMP x{BOMP_ITERS}, refinement of {BOMP_ITERS} cells"),
+            "grid_points_per_step": pts_step,
+            "gh_grid": list(s.grid.n),
+            "direct_grid": list(dgrid_s.n),
+            "interp": args.interp,
+        },
+        "rows_ms": {"rd_maps": t_maps * 1e3, "gh_sweep": t_sweep * 1e3, "argmax": t_arg * 1e3,
+                    "direct": t_dir * 1e3, "bomp_refine_rest": (t_total - t_maps - t_sweep - t_arg - t_dir) * 1e3},
+        "gh_points_per_s": n_gh / (t_maps + t_sweep + t_arg),
+        "gh_sweep_points_per_s": n_gh / t_sweep,
+        "direct_points_per_s": n_dir / t_dir,
+        "speedup_gh_over_direct_per_point": (n_gh / (t_maps + t_sweep + t_arg)) / (n_dir / t_dir),
+        "roofline": {"kernel": "gh_sweep_kernel<bilinear>" if interp == gh.BILINEAR else "gh_sweep_kernel<bicubic>",
+                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": sweep_bytes,
+                     "avg_launch_us": t_sweep * 1e6},
+    }
+
+    if not args.no_cpu_baseline:
+        rng = np.random.default_rng(2024)
+        gh_idx = rng.integers(0, n_gh, 2_000_000)
+        dir_idx = rng.integers(0, n_dir, 100_000)
+        torch.cuda.synchronize()
+        dv = dec.view(-1).cpu().numpy()
+        ddv = ddec.view(-1).cpu().numpy()
+        job = {"gh_idx": gh_idx, "dir_idx": dir_idx, "gh_gpu": dv[gh_idx].astype(np.float64),
+               "dir_gpu": ddv[dir_idx].astype(np.float64), "gh_max": np.float64(dv.max()),
+               "dir_max": np.float64(ddv.max()), "support": bomp.support.cpu().numpy(),
+               "interp": np.int64(interp)}
+        line["cpu_baseline"] = cpu_baseline(job)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -128,6 +128,12 @@ int gh_rd_maps(const gh_radar *radar, const void *d_y, void *d_maps, void *strea
 int gh_decision(const gh_radar *radar, const gh_grid *grid, const void *d_maps, int32_t interp,
                 float *d_decision, gh_peak *d_block, gh_peak *d_argmax, void *stream);
 
+/* Global maximum of per-location peaks (the argmax of eqs. (5)-(6) over the
+ * whole grid, from the block maxima gh_decision / gh_direct_decision write):
+ * largest value, ties to the lowest index.  d_block: gh_peak [n_block]
+ * (1 <= n_block < 2^31); d_argmax: gh_peak [1]. */
+int gh_argmax(const gh_peak *d_block, int64_t n_block, gh_peak *d_argmax, void *stream);
+
 /* Workspace of gh_direct_decision in bytes. */
 size_t gh_direct_workspace_bytes(const gh_radar *radar, const gh_grid *grid, int32_t gemm_dtype);
 

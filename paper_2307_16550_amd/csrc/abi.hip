@@ -165,6 +165,16 @@ int gh_decision(const gh_radar* radar, const gh_grid* grid, const void* d_maps, 
     return ok();
 }
 
+int gh_argmax(const gh_peak* d_block, int64_t n_block, gh_peak* d_argmax, void* stream) {
+    if (!d_block || !d_argmax) return fail(GH_EINVAL, "d_block and d_argmax must be non-NULL");
+    if (n_block < 1 || n_block >= (1LL << 31)) return fail(GH_EINVAL, "n_block must be in [1, 2^31)");
+    int rc = check_device();
+    if (rc) return rc;
+    hipError_t e = gh::launch_peak_final(d_block, (int)n_block, d_argmax, nullptr, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gh_argmax launch");
+    return ok();
+}
+
 size_t gh_direct_workspace_bytes(const gh_radar* radar, const gh_grid* grid, int32_t gemm_dtype) {
     gh::Geom g;
     gh::GridP gp;

@@ -22,7 +22,7 @@ BILINEAR, BICUBIC = 0, 1
 GEMM_F32, GEMM_BF16 = 0, 1
 MAX_SUPPORT = 32
 
-EXPORTS = ("gh_abi_version", "gh_last_error", "gh_rd_maps", "gh_decision", "gh_direct_workspace_bytes",
+EXPORTS = ("gh_abi_version", "gh_last_error", "gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_workspace_bytes",
            "gh_direct_decision", "gh_bomp_workspace_bytes", "gh_bomp_step", "gh_refine")
 
 
@@ -64,6 +64,7 @@ def load():
     lib.gh_last_error.restype = ctypes.c_char_p
     lib.gh_rd_maps.argtypes = [rp, vp, vp, vp]
     lib.gh_decision.argtypes = [rp, gp_, vp, i32, vp, pp, pp, vp]
+    lib.gh_argmax.argtypes = [pp, ctypes.c_int64, pp, vp]
     lib.gh_direct_workspace_bytes.argtypes = [rp, gp_, i32]
     lib.gh_direct_workspace_bytes.restype = sz
     lib.gh_direct_decision.argtypes = [rp, gp_, vp, i32, vp, sz, vp, pp, pp, vp]
@@ -71,7 +72,7 @@ def load():
     lib.gh_bomp_workspace_bytes.restype = sz
     lib.gh_bomp_step.argtypes = [rp, gp_, vp, vp, vp, i32, i32, i32, vp, i32, i32, vp, pp, vp, sz, vp]
     lib.gh_refine.argtypes = [rp, gp_, vp, vp, i32, i32, vp, vp]
-    for name in ("gh_rd_maps", "gh_decision", "gh_direct_decision", "gh_bomp_step", "gh_refine"):
+    for name in ("gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_decision", "gh_bomp_step", "gh_refine"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -158,7 +159,7 @@ def rd_maps(radar: Radar, y: torch.Tensor, maps: torch.Tensor | None = None, str
 
 
 def decision(radar: Radar, grid: GhGrid, maps, interp=BILINEAR, dec=None, block=None, argmax=None,
-             write_volume=True, stream=None):
+             write_volume=True, want_argmax=True, stream=None):
     lib = load()
     _c64(maps)
     nloc = grid.n[0] * grid.n[1]
@@ -166,11 +167,20 @@ def decision(radar: Radar, grid: GhGrid, maps, interp=BILINEAR, dec=None, block=
         dec = torch.empty(tuple(grid.n), dtype=torch.float32, device=maps.device)
     if block is None:
         block = peaks_tensor(nloc, maps.device)
-    if argmax is None:
+    if argmax is None and want_argmax:
         argmax = peaks_tensor(1, maps.device)
     _check(lib.gh_decision(ctypes.byref(radar.c_struct), ctypes.byref(grid), _ptr(maps), int(interp), _ptr(dec),
                            _ptr(block), _ptr(argmax), _stream(stream)))
     return dec, block, argmax
+
+
+def argmax(block: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    """Global maximum of a gh_peak buffer (value, index; ties to the lowest index)."""
+    lib = load()
+    if out is None:
+        out = peaks_tensor(1, block.device)
+    _check(lib.gh_argmax(_ptr(block), block.shape[0], _ptr(out), _stream(stream)))
+    return out
 
 
 def direct_workspace_bytes(radar: Radar, grid: GhGrid, gemm=GEMM_F32) -> int:
@@ -181,7 +191,7 @@ def direct_workspace_bytes(radar: Radar, grid: GhGrid, gemm=GEMM_F32) -> int:
 
 
 def direct_decision(radar: Radar, grid: GhGrid, y, gemm=GEMM_F32, ws=None, dec=None, block=None, argmax=None,
-                    write_volume=True, stream=None):
+                    write_volume=True, want_argmax=True, stream=None):
     lib = load()
     _c64(y)
     nloc = grid.n[0] * grid.n[1]
@@ -191,7 +201,7 @@ def direct_decision(radar: Radar, grid: GhGrid, y, gemm=GEMM_F32, ws=None, dec=N
         dec = torch.empty(tuple(grid.n), dtype=torch.float32, device=y.device)
     if block is None:
         block = peaks_tensor(nloc, y.device)
-    if argmax is None:
+    if argmax is None and want_argmax:
         argmax = peaks_tensor(1, y.device)
     _check(lib.gh_direct_decision(ctypes.byref(radar.c_struct), ctypes.byref(grid), _ptr(y), int(gemm), _ptr(ws),
                                   ws.numel(), _ptr(dec), _ptr(block), _ptr(argmax), _stream(stream)))
