@@ -24,8 +24,9 @@ with a single grid point is held fixed):
   step  = sum_i (e_i . g) / max(|lambda_i|, 1e-12 max|lambda|) e_i over the
           eigenpairs of the Hessian (the Newton step where the Hessian is
           negative definite, an ascent step everywhere);
+  stop if every component of the step is below `tol` cells;
   candidate = clamp(z + step, [-1, 1]); while D(candidate) < D(z), halve the
-          step (at most 30 times; no ascent -> stop);
+          step (at most 31 candidates; no ascent -> stop);
   stop when the accepted move is below `tol` cells or after `max_iter` steps.
 """
 from __future__ import annotations
@@ -125,6 +126,8 @@ def refine_one(y, radar: rd.Radar, theta0, h, max_iter: int = 20, tol: float = 1
         floor = 1e-12 * max(np.max(np.abs(lam)), 1e-300)
         step = vec @ ((vec.T @ gz) / np.maximum(np.abs(lam), floor))
         step = np.where(free, step, 0.0)
+        if float(np.max(np.abs(step))) < tol:
+            break
         accepted = False
         for _ in range(31):
             cand = np.clip(z + step, -1.0, 1.0)

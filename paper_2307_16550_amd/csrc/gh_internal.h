@@ -152,6 +152,13 @@ hipError_t launch_rd_maps(const Geom& g, const float2* y, float2* maps, hipStrea
 hipError_t launch_gh_sweep(const Geom& g, const GridP& gp, const float2* maps, int interp, float* dec,
                            gh_peak* block, const int64_t* excl, int nexcl, hipStream_t st);
 
+// Column variant of the sweep (power-of-two vy slabs); plan() returns false
+// when the shape needs the generic kernel.
+bool sweep_columns_plan(const Geom& g, const GridP& gp, int interp, int& lpb, int& log2nvy, size_t& lds);
+hipError_t launch_gh_sweep_columns(const Geom& g, const GridP& gp, int lpb, int log2nvy, size_t lds,
+                                   const float2* maps, int interp, float* dec, gh_peak* block, const int64_t* excl,
+                                   int nexcl, hipStream_t st);
+
 hipError_t launch_peak_final(const gh_peak* block, int nblock, gh_peak* out, int64_t* support_slot,
                              hipStream_t st);
 

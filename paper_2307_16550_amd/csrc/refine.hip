@@ -2,21 +2,28 @@
 // estimators stop at a cell).  One workgroup per starting cell runs the whole
 // Newton ascent on D(theta) = sum_q |c_q(theta)|^2 in-kernel:
 //   c_q = M_00, with moments M_pq = sum_{m,s} Y_q[m][s] E s^p m^q,
-//   E = exp(-j 2 pi (f_r s + f_d m)), reduced in FP64 over the frame;
+//   E = exp(-j 2 pi (f_r s + f_d m)) = e_r[s] e_d[m];
 //   dc/da = -j 2 pi (f_r,a M_10 + f_d,a M_01),
 //   d2c/da db = -4 pi^2 (f_r,a f_r,b M_20 + (f_r,a f_d,b + f_d,a f_r,b) M_11 + f_d,a f_d,b M_02)
 //               - j 2 pi (f_r,ab M_10 + f_d,ab M_01),
 // with the analytic derivatives of f_r = B R/(c Ms) and f_d = f0 Tc <w, v>/c
-// (eqs. (1)-(2)).  Coordinates are scaled by the grid steps (an axis with one
-// grid point is held); the step uses the Hessian's eigenpairs with
-// eigenvalues replaced by -|lambda| (cyclic Jacobi, FP64), halves until the
-// decision does not decrease (at most 31 tries), and is clamped to +-1 step.
+// (eqs. (1)-(2)).  The atom is separable, so the moments are two reductions:
+// per chirp A_p[m] = sum_s s^p e_r[s] Y[m][s] (p <= 2), then
+// M_pq = sum_m m^q e_d[m] A_p[m]; only Ms + Mc phase factors are evaluated per
+// receiver (32-bit fixed-point phases, FP64 accumulation).
+// Coordinates are scaled by the grid steps (an axis with one grid point is
+// held); the step uses the Hessian's eigenpairs with eigenvalues replaced by
+// -|lambda| (cyclic Jacobi, FP64); the ascent stops when every step component
+// is below 1e-7 steps; otherwise the step is halved until the decision does
+// not decrease (at most 31 candidates) and clamped to +-1 grid step.
 #include "gh_internal.h"
 
 namespace gh {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 1024;
+constexpr int kWaves = kThreads / 64;
+constexpr double kTol = 1e-7;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -109,56 +116,122 @@ __device__ void jacobi4(double a[4][4], double v[4][4]) {
     }
 }
 
-// Workgroup-wide moment sums for receiver q at phases (frx, fdx).  With
-// full == false only M_00 is reduced.  Result broadcast through `out`.
+constexpr int kChunk = 256;    // chirp rows per stage-A pass
+
+struct Scratch {
+    float2 er[1024];           // exp(-j 2 pi f_r s)
+    float2 ed[1024];           // exp(-j 2 pi f_d m)
+    double2 a[3][kChunk];      // A_p[m] of the current chunk of chirps
+    double red[kWaves][12];
+};
+
+// Workgroup-wide moments of receiver q at phases (frx, fdx).  full == false:
+// only M_00.  Result (12 doubles: re/im of M00, M10, M01, M20, M11, M02)
+// broadcast through `out`.
 __device__ void moments(const Geom& g, const float2* __restrict__ yq, uint32_t frx, uint32_t fdx, bool full,
-                        double* red /*[4][12]*/, double* out /*[12]*/) {
+                        Scratch& sc, double* out) {
+    const int tid = threadIdx.x;
+    const int ms = g.ms, mc = g.mc;
+    __syncthreads();
+    for (int s = tid; s < ms; s += kThreads) sc.er[s] = expm_fixed(frx * (uint32_t)s);
+    for (int m = tid; m < mc; m += kThreads) sc.ed[m] = expm_fixed(fdx * (uint32_t)m);
+    __syncthreads();
     double acc[12];
     for (int i = 0; i < 12; ++i) acc[i] = 0.0;
-    const int n = g.mc * g.ms;
-    for (int e = threadIdx.x; e < n; e += kThreads) {
-        const uint32_t m = (uint32_t)(e >> g.log2_ms), s = (uint32_t)(e & (g.ms - 1));
-        const float2 ex = expm_fixed(frx * s + fdx * m);
-        const float2 v = yq[e];
-        const double re = (double)v.x * ex.x - (double)v.y * ex.y;
-        const double im = (double)v.x * ex.y + (double)v.y * ex.x;
-        acc[0] += re;
-        acc[1] += im;
-        if (full) {
-            const double ds = (double)s, dm = (double)m;
-            acc[2] += re * ds;
-            acc[3] += im * ds;
-            acc[4] += re * dm;
-            acc[5] += im * dm;
-            acc[6] += re * ds * ds;
-            acc[7] += im * ds * ds;
-            acc[8] += re * ds * dm;
-            acc[9] += im * ds * dm;
-            acc[10] += re * dm * dm;
-            acc[11] += im * dm * dm;
+    const int rows = mc < kChunk ? mc : kChunk;
+    // stage A: `tpr` lanes per chirp row (power of two, at most one wave)
+    int tpr = kThreads / rows;
+    if (tpr > 64) tpr = 64;
+    const int lane = tid & (tpr - 1);
+    for (int c0 = 0; c0 < mc; c0 += rows) {
+      {
+        const int m = c0 + tid / tpr;      // kThreads / tpr >= rows: one pass covers the chunk
+        double a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0;
+        if (tid / tpr < rows) {
+            const float2* row = yq + (size_t)m * ms;
+            for (int s = lane; s < ms; s += tpr) {
+                const float2 v = row[s], e = sc.er[s];
+                const double re = (double)v.x * e.x - (double)v.y * e.y;
+                const double im = (double)v.x * e.y + (double)v.y * e.x;
+                a0r += re;
+                a0i += im;
+                if (full) {
+                    const double ds = (double)s;
+                    a1r += re * ds;
+                    a1i += im * ds;
+                    a2r += re * ds * ds;
+                    a2i += im * ds * ds;
+                }
+            }
         }
+        for (int off = tpr >> 1; off >= 1; off >>= 1) {
+            a0r += __shfl_xor(a0r, off, 64);
+            a0i += __shfl_xor(a0i, off, 64);
+            if (full) {
+                a1r += __shfl_xor(a1r, off, 64);
+                a1i += __shfl_xor(a1i, off, 64);
+                a2r += __shfl_xor(a2r, off, 64);
+                a2i += __shfl_xor(a2i, off, 64);
+            }
+        }
+        if (tid / tpr < rows && lane == 0) {
+            sc.a[0][m - c0] = make_double2(a0r, a0i);
+            sc.a[1][m - c0] = make_double2(a1r, a1i);
+            sc.a[2][m - c0] = make_double2(a2r, a2i);
+        }
+      }
+      __syncthreads();
+      // stage B: sum over the chunk's chirps with the Doppler factors
+      if (tid < rows) {
+        const int m = c0 + tid;
+        const float2 e = sc.ed[m];
+        const double dm = (double)m;
+        for (int p = 0; p < (full ? 3 : 1); ++p) {
+            const double2 a = sc.a[p][tid];
+            const double re = a.x * e.x - a.y * e.y;
+            const double im = a.x * e.y + a.y * e.x;
+            if (p == 0) {
+                acc[0] += re;
+                acc[1] += im;
+                if (full) {
+                    acc[4] += re * dm;
+                    acc[5] += im * dm;
+                    acc[10] += re * dm * dm;
+                    acc[11] += im * dm * dm;
+                }
+            } else if (p == 1) {
+                acc[2] += re;
+                acc[3] += im;
+                acc[8] += re * dm;
+                acc[9] += im * dm;
+            } else {
+                acc[6] += re;
+                acc[7] += im;
+            }
+        }
+      }
+      __syncthreads();
     }
     const int cnt = full ? 12 : 2;
-    __syncthreads();
     for (int i = 0; i < cnt; ++i) {
         const double s = wave_sum(acc[i]);
-        if ((threadIdx.x & 63) == 0) red[(threadIdx.x >> 6) * 12 + i] = s;
+        if ((tid & 63) == 0) sc.red[tid >> 6][i] = s;
     }
     __syncthreads();
-    if (threadIdx.x < cnt) {
+    if (tid < cnt) {
         double t = 0.0;
-        for (int w = 0; w < kThreads / 64; ++w) t += red[w * 12 + threadIdx.x];
-        out[threadIdx.x] = t;
+        for (int w = 0; w < kWaves; ++w) t += sc.red[w][tid];
+        out[tid] = t;
     }
     __syncthreads();
 }
 
-__device__ double decision_at(const Geom& g, const float2* y, const double th[4], double* red, double* mom) {
+__device__ double decision_at(const Geom& g, const float2* y, const double th[4], Scratch& sc, double* mom) {
     double dsum = 0.0;
     for (int q = 0; q < g.k; ++q) {
         FreqD fq;
         freq_derivs(g, q, th, fq);
-        moments(g, y + (size_t)q * g.mc * g.ms, cycles_to_fixed(fq.fr), cycles_to_fixed(fq.fd), false, red, mom);
+        moments(g, y + (size_t)q * g.mc * g.ms, cycles_to_fixed(fq.fr), cycles_to_fixed(fq.fd), false, sc, mom);
         dsum += mom[0] * mom[0] + mom[1] * mom[1];
     }
     return dsum;
@@ -167,11 +240,9 @@ __device__ double decision_at(const Geom& g, const float2* y, const double th[4]
 __global__ __launch_bounds__(kThreads) void refine_kernel(Geom g, GridP gp, const float2* __restrict__ y,
                                                          const int64_t* __restrict__ cells, int max_iter,
                                                          double* __restrict__ theta_out) {
-    __shared__ double red[4 * 12];
+    __shared__ Scratch sc;
     __shared__ double mom[kMaxRx][12];
     __shared__ double sh_step[4];
-    __shared__ double sh_cand[4];
-    __shared__ int sh_flag;
     const int tid = threadIdx.x;
     int64_t idx = cells[blockIdx.x];
     const int ivy = (int)(idx % gp.n[3]);
@@ -184,7 +255,7 @@ __global__ __launch_bounds__(kThreads) void refine_kernel(Geom g, GridP gp, cons
                            gp.lo[3] + ivy * gp.step[3]};
     const double* h = gp.step;
     double z[4] = {0, 0, 0, 0};
-    double d_cur = decision_at(g, y, th0, red, mom[0]);
+    double d_cur = decision_at(g, y, th0, sc, mom[0]);
     const double tp = 6.283185307179586;
     for (int it = 0; it < max_iter; ++it) {
         double th[4];
@@ -192,7 +263,7 @@ __global__ __launch_bounds__(kThreads) void refine_kernel(Geom g, GridP gp, cons
         for (int q = 0; q < g.k; ++q) {
             FreqD fq;
             freq_derivs(g, q, th, fq);
-            moments(g, y + (size_t)q * g.mc * g.ms, cycles_to_fixed(fq.fr), cycles_to_fixed(fq.fd), true, red,
+            moments(g, y + (size_t)q * g.mc * g.ms, cycles_to_fixed(fq.fr), cycles_to_fixed(fq.fd), true, sc,
                     mom[q]);
         }
         if (tid == 0) {
@@ -203,12 +274,11 @@ __global__ __launch_bounds__(kThreads) void refine_kernel(Geom g, GridP gp, cons
                 FreqD f;
                 freq_derivs(g, q, th, f);
                 const double* mo = mom[q];
-                // dc[a] = -j 2 pi (gr M10 + gd M01)
                 double dcr[4], dci[4];
                 for (int a = 0; a < 4; ++a) {
                     const double tr = f.gr[a] * mo[2] + f.gd[a] * mo[4];
                     const double ti = f.gr[a] * mo[3] + f.gd[a] * mo[5];
-                    dcr[a] = tp * ti;
+                    dcr[a] = tp * ti;        // -j 2 pi (tr + j ti)
                     dci[a] = -tp * tr;
                 }
                 const double cr = mo[0], ci = mo[1];
@@ -221,10 +291,8 @@ __global__ __launch_bounds__(kThreads) void refine_kernel(Geom g, GridP gp, cons
                         const double pi = k20 * mo[7] + k11 * mo[9] + k02 * mo[11];
                         const double sr = f.hr[a][b] * mo[2] + f.hd[a][b] * mo[4];
                         const double si = f.hr[a][b] * mo[3] + f.hd[a][b] * mo[5];
-                        // d2c = -tp^2 (pr + j pi) - j tp (sr + j si)
-                        const double d2r = -tp * tp * pr + tp * si;
+                        const double d2r = -tp * tp * pr + tp * si;     // -tp^2 (pr + j pi) - j tp (sr + j si)
                         const double d2i = -tp * tp * pi - tp * sr;
-                        // 2 Re(dc_a conj(dc_b) + conj(c) d2c)
                         hess[a][b] += 2.0 * (dcr[a] * dcr[b] + dci[a] * dci[b] + cr * d2r + ci * d2i);
                     }
                 }
@@ -251,15 +319,19 @@ __global__ __launch_bounds__(kThreads) void refine_kernel(Geom g, GridP gp, cons
             }
         }
         __syncthreads();
-        double step[4];
-        for (int a = 0; a < 4; ++a) step[a] = sh_step[a];
+        double step[4], smax = 0.0;
+        for (int a = 0; a < 4; ++a) {
+            step[a] = sh_step[a];
+            smax = fmax(smax, fabs(step[a]));
+        }
+        if (smax < kTol) break;
         bool accepted = false;
         double cand[4], d_new = 0.0;
         for (int tries = 0; tries < 31; ++tries) {
             for (int a = 0; a < 4; ++a) cand[a] = fmin(1.0, fmax(-1.0, z[a] + step[a]));
             double thc[4];
             for (int a = 0; a < 4; ++a) thc[a] = th0[a] + cand[a] * h[a];
-            d_new = decision_at(g, y, thc, red, mom[0]);
+            d_new = decision_at(g, y, thc, sc, mom[0]);
             if (d_new >= d_cur) {
                 accepted = true;
                 break;
@@ -273,12 +345,10 @@ __global__ __launch_bounds__(kThreads) void refine_kernel(Geom g, GridP gp, cons
             z[a] = cand[a];
         }
         d_cur = d_new;
-        if (move < 1e-7) break;
+        if (move < kTol) break;
     }
     if (tid == 0)
         for (int a = 0; a < 4; ++a) theta_out[(size_t)blockIdx.x * 4 + a] = th0[a] + z[a] * h[a];
-    (void)sh_cand;
-    (void)sh_flag;
 }
 
 }  // namespace

@@ -217,6 +217,10 @@ __global__ __launch_bounds__(1024) void peak_final_kernel(const gh_peak* __restr
 
 hipError_t launch_gh_sweep(const Geom& g, const GridP& gp, const float2* maps, int interp, float* dec,
                            gh_peak* block, const int64_t* excl, int nexcl, hipStream_t st) {
+    int lpb = 0, log2nvy = 0;
+    size_t lds_cols = 0;
+    if (sweep_columns_plan(g, gp, interp, lpb, log2nvy, lds_cols))
+        return launch_gh_sweep_columns(g, gp, lpb, log2nvy, lds_cols, maps, interp, dec, block, excl, nexcl, st);
     const size_t lds = (size_t)g.nd * (interp ? 32 : 16) + (size_t)g.nd * 8;
     if (interp == GH_INTERP_BICUBIC)
         hipLaunchKernelGGL(gh_sweep_kernel<1>, dim3(gp.nloc), dim3(kThreads), lds, st, g, gp, maps, dec, block,

@@ -176,6 +176,27 @@ def test_gh_ragged_and_degenerate_grids(n, interp):
     check_argmax(lambda i: dr.ravel()[i], int(ai[0]), ref_idx, ref_val, f"ragged {n}")
 
 
+@pytest.mark.parametrize("ms,mc,n", [(64, 32, (7, 9, 16, 8)), (64, 32, (3, 5, 32, 64)), (64, 32, (2, 7, 5, 16)),
+                                     (128, 256, (5, 6, 32, 32)), (64, 512, (3, 4, 9, 8)), (32, 8, (6, 5, 32, 32))])
+@pytest.mark.parametrize("interp", [gh.BILINEAR, gh.BICUBIC])
+def test_gh_column_kernel_shapes(ms, mc, n, interp):
+    """Power-of-two vy slabs (the column kernel): ragged location tails, short vx, N_d above 512."""
+    say(f"gh columns ms={ms} mc={mc} n={n} interp={interp}")
+    s, r, gr = scene_and_radar(1, 8, ms=ms, mc=mc)
+    grid = sc.Grid((5.5, -9.0, -12.0, -11.0), (23.0, 9.5, 12.5, 11.0), n)
+    zd = gh.rd_maps(gr, to_dev(s.y))
+    dec, block, arg = gh.decision(gr, gh.grid_of(grid), zd, interp)
+    dg = dec.cpu().numpy().astype(np.float64)
+    z = omaps.rd_maps(s.y, r.pad_r, r.pad_d, r.centered)
+    dr = ogh.gh_decision(z, r, grid, interp)
+    assert np.max(np.abs(dg - dr)) / dr.max() <= DEC_TOL
+    bv, bi = gh.decode_peaks(block)
+    assert np.array_equal(bv, dg.reshape(len(bv), -1).max(axis=1).astype(np.float32))
+    _, ai = gh.decode_peaks(arg)
+    ref_val, ref_idx = opeaks.global_peak(dr)
+    check_argmax(lambda i: dr.ravel()[i], int(ai[0]), ref_idx, ref_val, f"columns {n}")
+
+
 def test_gh_wrapping_range_rows_and_doppler_seam():
     """Locations whose range coordinate sits at the edge of the map and velocities across the Doppler seam."""
     s, r, gr = scene_and_radar(1, 4)
