@@ -19,6 +19,9 @@
 // Per (point, receiver) the hot loop is then: integer coordinate, one LDS
 // table read, a complex Horner step and |.|^2.
 // Taps beyond one period of a centred map pick up the factor (-1)^(M-1).
+#include <stdlib.h>
+#include <string.h>
+
 #include "gh_internal.h"
 
 namespace gh {
@@ -217,9 +220,15 @@ __global__ __launch_bounds__(1024) void peak_final_kernel(const gh_peak* __restr
 
 hipError_t launch_gh_sweep(const Geom& g, const GridP& gp, const float2* maps, int interp, float* dec,
                            gh_peak* block, const int64_t* excl, int nexcl, hipStream_t st) {
+    // GH_SWEEP_KERNEL = columns | generic restricts the variant (diagnostics and tuning)
+    static const int only = [] {
+        const char* s = getenv("GH_SWEEP_KERNEL");
+        if (!s) return 0;
+        return strcmp(s, "columns") == 0 ? 2 : strcmp(s, "generic") == 0 ? 3 : 0;
+    }();
     int lpb = 0, log2nvy = 0;
     size_t lds_cols = 0;
-    if (sweep_columns_plan(g, gp, interp, lpb, log2nvy, lds_cols))
+    if ((only == 0 || only == 2) && sweep_columns_plan(g, gp, interp, lpb, log2nvy, lds_cols))
         return launch_gh_sweep_columns(g, gp, lpb, log2nvy, lds_cols, maps, interp, dec, block, excl, nexcl, st);
     const size_t lds = (size_t)g.nd * (interp ? 32 : 16) + (size_t)g.nd * 8;
     if (interp == GH_INTERP_BICUBIC)

@@ -177,7 +177,8 @@ def test_gh_ragged_and_degenerate_grids(n, interp):
 
 
 @pytest.mark.parametrize("ms,mc,n", [(64, 32, (7, 9, 16, 8)), (64, 32, (3, 5, 32, 64)), (64, 32, (2, 7, 5, 16)),
-                                     (128, 256, (5, 6, 32, 32)), (16, 128, (3, 4, 9, 8)), (32, 8, (6, 5, 32, 32))])
+                                     (128, 256, (5, 6, 32, 32)), (16, 128, (3, 4, 9, 8)), (32, 8, (6, 5, 32, 32)),
+                                     (64, 32, (3, 4, 33, 2)), (64, 32, (2, 3, 40, 1)), (64, 32, (5, 5, 17, 4))])
 @pytest.mark.parametrize("interp", [gh.BILINEAR, gh.BICUBIC])
 def test_gh_column_kernel_shapes(ms, mc, n, interp):
     """Power-of-two vy slabs (the column kernel): ragged location tails, short vx, N_d above 512."""
