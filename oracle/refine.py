@@ -26,7 +26,7 @@ with a single grid point is held fixed):
           negative definite, an ascent step everywhere);
   stop if every component of the step is below `tol` cells;
   candidate = clamp(z + step, [-1, 1]); while D(candidate) < D(z), halve the
-          step (at most 31 candidates; no ascent -> stop);
+          step (at most 16 candidates; no ascent -> stop);
   stop when the accepted move is below `tol` cells or after `max_iter` steps.
 """
 from __future__ import annotations
@@ -129,7 +129,7 @@ def refine_one(y, radar: rd.Radar, theta0, h, max_iter: int = 20, tol: float = 1
         if float(np.max(np.abs(step))) < tol:
             break
         accepted = False
-        for _ in range(31):
+        for _ in range(16):
             cand = np.clip(z + step, -1.0, 1.0)
             d_new = decision_value(y, radar, theta0 + cand * h)
             if d_new >= d_cur:

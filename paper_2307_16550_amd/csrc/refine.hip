@@ -10,103 +10,128 @@
 // (eqs. (1)-(2)).  The atom is separable, so the moments are two reductions:
 // per chirp A_p[m] = sum_s s^p e_r[s] Y[m][s] (p <= 2), then
 // M_pq = sum_m m^q e_d[m] A_p[m]; only Ms + Mc phase factors are evaluated per
-// receiver (32-bit fixed-point phases, FP64 accumulation).
+// receiver (32-bit fixed-point phases, FP64 accumulation).  All receivers
+// (or as many as the scratch holds) share one pass: their (receiver, chirp)
+// rows are spread over the workgroup and reduced by segment.
 // Coordinates are scaled by the grid steps (an axis with one grid point is
 // held); the step uses the Hessian's eigenpairs with eigenvalues replaced by
 // -|lambda| (cyclic Jacobi, FP64); the ascent stops when every step component
 // is below 1e-7 steps; otherwise the step is halved until the decision does
-// not decrease (at most 31 candidates) and clamped to +-1 grid step.
+// not decrease (at most 16 candidates) and clamped to +-1 grid step.
 #include "gh_internal.h"
 
 namespace gh {
 namespace {
 
 constexpr int kThreads = 1024;
-constexpr int kWaves = kThreads / 64;
 constexpr double kTol = 1e-7;
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-struct FreqD {
+// f_r, f_d and their first and second derivatives, kept to the structurally
+// nonzero entries: f_r depends on (x, y) only, f_d is linear in v, and
+// d2 f_d / dx dv = beta_d J with J symmetric.
+struct FreqC {
     double fr, fd;
-    double gr[4], gd[4];
-    double hr[4][4], hd[4][4];
+    double gr0, gr1;                 // d f_r / d(x, y)
+    double gd0, gd1, gd2, gd3;       // d f_d / d(x, y, vx, vy)
+    double hr00, hr01, hr11;         // d2 f_r / dx dx
+    double hd00, hd01, hd11;         // d2 f_d / dx dx
+    double hj00, hj01, hj11;         // d2 f_d / dx dv
 };
 
-__device__ void freq_derivs(const Geom& g, int q, const double th[4], FreqD& o) {
+__device__ __forceinline__ double gr_at(const FreqC& f, int a) { return a == 0 ? f.gr0 : (a == 1 ? f.gr1 : 0.0); }
+__device__ __forceinline__ double gd_at(const FreqC& f, int a) {
+    return a == 0 ? f.gd0 : (a == 1 ? f.gd1 : (a == 2 ? f.gd2 : f.gd3));
+}
+__device__ __forceinline__ double hr_at(const FreqC& f, int a, int b) {
+    if (a > 1 || b > 1) return 0.0;
+    return a != b ? f.hr01 : (a == 0 ? f.hr00 : f.hr11);
+}
+__device__ __forceinline__ double hd_at(const FreqC& f, int a, int b) {
+    if (a < 2 && b < 2) return a != b ? f.hd01 : (a == 0 ? f.hd00 : f.hd11);
+    if (a >= 2 && b >= 2) return 0.0;
+    const int i = a < 2 ? a : b, j = (a < 2 ? b : a) - 2;
+    return i != j ? f.hj01 : (i == 0 ? f.hj00 : f.hj11);
+}
+
+__device__ __forceinline__ void freq_compact(const Geom& g, int q, const double th[4], FreqC& o) {
     const double beta_r = g.fr_per_m, beta_d = g.fd_per_mps;
-    double w[2] = {0, 0}, jac[2][2] = {{0, 0}, {0, 0}}, hxx[2][2] = {{0, 0}, {0, 0}}, rsum = 0;
-    const double v[2] = {th[2], th[3]};
+    double w0 = 0, w1 = 0, j00 = 0, j01 = 0, j11 = 0, x00 = 0, x01 = 0, x11 = 0, rsum = 0;
+    const double v0 = th[2], v1 = th[3];
+#pragma unroll
     for (int leg = 0; leg < 2; ++leg) {
         const double ax = leg ? g.rx[q][0] : g.tx[0];
         const double ay = leg ? g.rx[q][1] : g.tx[1];
-        const double d[2] = {th[0] - ax, th[1] - ay};
-        const double rho = sqrt(d[0] * d[0] + d[1] * d[1]);
+        const double d0 = th[0] - ax, d1 = th[1] - ay;
+        const double rho = sqrt(d0 * d0 + d1 * d1);
         if (rho == 0.0) continue;
-        const double u[2] = {d[0] / rho, d[1] / rho};
+        const double u0 = d0 / rho, u1 = d1 / rho, inv = 1.0 / rho, inv2 = inv * inv;
+        const double uv = u0 * v0 + u1 * v1;
         rsum += rho;
-        w[0] += u[0];
-        w[1] += u[1];
-        const double uv = u[0] * v[0] + u[1] * v[1];
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) {
-                const double delta = (a == b) ? 1.0 : 0.0;
-                jac[a][b] += (delta - u[a] * u[b]) / rho;
-                hxx[a][b] -= (v[a] * u[b] + u[a] * v[b] + uv * (delta - 3.0 * u[a] * u[b])) / (rho * rho);
-            }
+        w0 += u0;
+        w1 += u1;
+        j00 += (1.0 - u0 * u0) * inv;
+        j01 += -u0 * u1 * inv;
+        j11 += (1.0 - u1 * u1) * inv;
+        x00 -= (2.0 * v0 * u0 + uv * (1.0 - 3.0 * u0 * u0)) * inv2;
+        x01 -= (v0 * u1 + u0 * v1 - uv * 3.0 * u0 * u1) * inv2;
+        x11 -= (2.0 * v1 * u1 + uv * (1.0 - 3.0 * u1 * u1)) * inv2;
     }
     o.fr = beta_r * rsum;
-    o.fd = beta_d * (w[0] * v[0] + w[1] * v[1]);
-    for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b) o.hr[a][b] = o.hd[a][b] = 0.0;
-    o.gr[0] = beta_r * w[0];
-    o.gr[1] = beta_r * w[1];
-    o.gr[2] = o.gr[3] = 0.0;
-    o.gd[0] = beta_d * (jac[0][0] * v[0] + jac[0][1] * v[1]);
-    o.gd[1] = beta_d * (jac[1][0] * v[0] + jac[1][1] * v[1]);
-    o.gd[2] = beta_d * w[0];
-    o.gd[3] = beta_d * w[1];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) {
-            o.hr[a][b] = beta_r * jac[a][b];
-            o.hd[a][b] = beta_d * hxx[a][b];
-            o.hd[a][2 + b] = beta_d * jac[a][b];
-            o.hd[2 + b][a] = beta_d * jac[b][a];
-        }
+    o.fd = beta_d * (w0 * v0 + w1 * v1);
+    o.gr0 = beta_r * w0;
+    o.gr1 = beta_r * w1;
+    o.gd0 = beta_d * (j00 * v0 + j01 * v1);
+    o.gd1 = beta_d * (j01 * v0 + j11 * v1);
+    o.gd2 = beta_d * w0;
+    o.gd3 = beta_d * w1;
+    o.hr00 = beta_r * j00;
+    o.hr01 = beta_r * j01;
+    o.hr11 = beta_r * j11;
+    o.hd00 = beta_d * x00;
+    o.hd01 = beta_d * x01;
+    o.hd11 = beta_d * x11;
+    o.hj00 = beta_d * j00;
+    o.hj01 = beta_d * j01;
+    o.hj11 = beta_d * j11;
 }
 
 // Cyclic Jacobi eigen-decomposition of a symmetric 4x4 matrix (a is destroyed:
 // its diagonal ends up holding the eigenvalues; v holds eigenvectors as columns).
-__device__ void jacobi4(double a[4][4], double v[4][4]) {
+__device__ __forceinline__ void jacobi4(double a[4][4], double v[4][4]) {
+#pragma unroll
     for (int i = 0; i < 4; ++i)
+#pragma unroll
         for (int j = 0; j < 4; ++j) v[i][j] = (i == j) ? 1.0 : 0.0;
     for (int sweep = 0; sweep < 50; ++sweep) {
         double off = 0.0, diag = 0.0;
+#pragma unroll
         for (int i = 0; i < 4; ++i) {
             diag += a[i][i] * a[i][i];
+#pragma unroll
             for (int j = i + 1; j < 4; ++j) off += a[i][j] * a[i][j];
         }
         if (off <= 1e-32 * diag || off == 0.0) break;
+#pragma unroll
         for (int p = 0; p < 3; ++p)
+#pragma unroll
             for (int q = p + 1; q < 4; ++q) {
                 if (a[p][q] == 0.0) continue;
                 const double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
                 const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
                 const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+#pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const double akp = a[k][p], akq = a[k][q];
                     a[k][p] = c * akp - s * akq;
                     a[k][q] = s * akp + c * akq;
                 }
+#pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const double apk = a[p][k], aqk = a[q][k];
                     a[p][k] = c * apk - s * aqk;
                     a[q][k] = s * apk + c * aqk;
                 }
+#pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const double vkp = v[k][p], vkq = v[k][q];
                     v[k][p] = c * vkp - s * vkq;
@@ -116,41 +141,59 @@ __device__ void jacobi4(double a[4][4], double v[4][4]) {
     }
 }
 
-constexpr int kChunk = 256;    // chirp rows per stage-A pass
+constexpr int kTab = 3072;       // phase factors of one receiver group (e_r then e_d per receiver)
+constexpr int kRowsMax = 512;    // (receiver, chirp) rows per group
+constexpr int kSegMax = 64;      // reduction segments per group
 
 struct Scratch {
-    float2 er[1024];           // exp(-j 2 pi f_r s)
-    float2 ed[1024];           // exp(-j 2 pi f_d m)
-    double2 a[3][kChunk];      // A_p[m] of the current chunk of chirps
-    double red[kWaves][12];
+    float2 tab[kTab];
+    double2 a[3][kRowsMax];      // A_p of each row
+    double seg[kSegMax][12];     // per-segment partial moments
+    uint32_t frx[kMaxRx], fdx[kMaxRx];
 };
 
-// Workgroup-wide moments of receiver q at phases (frx, fdx).  full == false:
-// only M_00.  Result (12 doubles: re/im of M00, M10, M01, M20, M11, M02)
-// broadcast through `out`.
-__device__ void moments(const Geom& g, const float2* __restrict__ yq, uint32_t frx, uint32_t fdx, bool full,
-                        Scratch& sc, double* out) {
+// Receivers per pass: the group's phase tables and rows must fit the scratch.
+__device__ __forceinline__ int group_size(const Geom& g) {
+    int gs = kTab / (g.ms + g.mc);
+    const int by_rows = kRowsMax / g.mc;
+    if (by_rows < gs) gs = by_rows;
+    if (gs > g.k) gs = g.k;
+    return gs < 1 ? 1 : gs;
+}
+
+// Workgroup-wide moments of receivers [q0, q0 + G) at theta, all in one pass:
+// out[q][0..11] = re/im of M00, M10, M01, M20, M11, M02 (full) or M00 only.
+__device__ __forceinline__ void moments_group(const Geom& g, const float2* __restrict__ y, const double th[4], int q0, int G,
+                              bool full, Scratch& sc, double (*out)[12]) {
     const int tid = threadIdx.x;
-    const int ms = g.ms, mc = g.mc;
+    const int ms = g.ms, mc = g.mc, span = ms + mc;
+    if (tid < G) {
+        FreqC f;
+        freq_compact(g, q0 + tid, th, f);
+        sc.frx[tid] = cycles_to_fixed(f.fr);
+        sc.fdx[tid] = cycles_to_fixed(f.fd);
+    }
     __syncthreads();
-    for (int s = tid; s < ms; s += kThreads) sc.er[s] = expm_fixed(frx * (uint32_t)s);
-    for (int m = tid; m < mc; m += kThreads) sc.ed[m] = expm_fixed(fdx * (uint32_t)m);
+    for (int e = tid; e < G * span; e += kThreads) {
+        const int qq = e / span, r = e - qq * span;
+        sc.tab[e] = (r < ms) ? expm_fixed(sc.frx[qq] * (uint32_t)r) : expm_fixed(sc.fdx[qq] * (uint32_t)(r - ms));
+    }
     __syncthreads();
-    double acc[12];
-    for (int i = 0; i < 12; ++i) acc[i] = 0.0;
-    const int rows = mc < kChunk ? mc : kChunk;
-    // stage A: `tpr` lanes per chirp row (power of two, at most one wave)
-    int tpr = kThreads / rows;
-    if (tpr > 64) tpr = 64;
+    // stage A: tpr lanes per (receiver, chirp) row, sums over fast time
+    const int rows = G * mc;
+    int tpr = 1;
+    while (tpr * 2 * rows <= kThreads && tpr < 64) tpr *= 2;
     const int lane = tid & (tpr - 1);
-    for (int c0 = 0; c0 < mc; c0 += rows) {
-      {
-        const int m = c0 + tid / tpr;      // kThreads / tpr >= rows: one pass covers the chunk
+    const int row = tid / tpr;
+    {
         double a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0;
-        if (tid / tpr < rows) {
-            const float2* row = yq + (size_t)m * ms;
+        if (row < rows) {
+            const int qq = row / mc, m = row - qq * mc;
+            const float2* yr = y + ((size_t)(q0 + qq) * mc + m) * ms;
+            const float2* er = sc.tab + qq * span;
+#pragma unroll 8
             for (int s = lane; s < ms; s += tpr) {
-                const float2 v = row[s], e = sc.er[s];
+                const float2 v = yr[s], e = er[s];
                 const double re = (double)v.x * e.x - (double)v.y * e.y;
                 const double im = (double)v.x * e.y + (double)v.y * e.x;
                 a0r += re;
@@ -174,66 +217,66 @@ __device__ void moments(const Geom& g, const float2* __restrict__ yq, uint32_t f
                 a2i += __shfl_xor(a2i, off, 64);
             }
         }
-        if (tid / tpr < rows && lane == 0) {
-            sc.a[0][m - c0] = make_double2(a0r, a0i);
-            sc.a[1][m - c0] = make_double2(a1r, a1i);
-            sc.a[2][m - c0] = make_double2(a2r, a2i);
+        if (row < rows && lane == 0) {
+            sc.a[0][row] = make_double2(a0r, a0i);
+            sc.a[1][row] = make_double2(a1r, a1i);
+            sc.a[2][row] = make_double2(a2r, a2i);
         }
-      }
-      __syncthreads();
-      // stage B: sum over the chunk's chirps with the Doppler factors
-      if (tid < rows) {
-        const int m = c0 + tid;
-        const float2 e = sc.ed[m];
+    }
+    __syncthreads();
+    // stage B: Doppler factors, then a segmented reduction over each receiver's chirps
+    double acc[12];
+    for (int i = 0; i < 12; ++i) acc[i] = 0.0;
+    if (tid < rows) {
+        const int qq = tid / mc, m = tid - qq * mc;
+        const float2 e = sc.tab[qq * span + ms + m];
         const double dm = (double)m;
         for (int p = 0; p < (full ? 3 : 1); ++p) {
             const double2 a = sc.a[p][tid];
             const double re = a.x * e.x - a.y * e.y;
             const double im = a.x * e.y + a.y * e.x;
             if (p == 0) {
-                acc[0] += re;
-                acc[1] += im;
+                acc[0] = re;
+                acc[1] = im;
                 if (full) {
-                    acc[4] += re * dm;
-                    acc[5] += im * dm;
-                    acc[10] += re * dm * dm;
-                    acc[11] += im * dm * dm;
+                    acc[4] = re * dm;
+                    acc[5] = im * dm;
+                    acc[10] = re * dm * dm;
+                    acc[11] = im * dm * dm;
                 }
             } else if (p == 1) {
-                acc[2] += re;
-                acc[3] += im;
-                acc[8] += re * dm;
-                acc[9] += im * dm;
+                acc[2] = re;
+                acc[3] = im;
+                acc[8] = re * dm;
+                acc[9] = im * dm;
             } else {
-                acc[6] += re;
-                acc[7] += im;
+                acc[6] = re;
+                acc[7] = im;
             }
         }
-      }
-      __syncthreads();
     }
     const int cnt = full ? 12 : 2;
-    for (int i = 0; i < cnt; ++i) {
-        const double s = wave_sum(acc[i]);
-        if ((tid & 63) == 0) sc.red[tid >> 6][i] = s;
-    }
+    const int seg = mc < 64 ? mc : 64;                // rows of one receiver are contiguous and wave-aligned
+    for (int i = 0; i < cnt; ++i)
+        for (int off = seg >> 1; off >= 1; off >>= 1) acc[i] += __shfl_xor(acc[i], off, 64);
+    if (tid < rows && (tid & (seg - 1)) == 0)
+        for (int i = 0; i < cnt; ++i) sc.seg[tid / seg][i] = acc[i];
     __syncthreads();
-    if (tid < cnt) {
+    const int per_q = mc / seg;
+    if (tid < G * cnt) {
+        const int qq = tid / cnt, c = tid - qq * cnt;
         double t = 0.0;
-        for (int w = 0; w < kWaves; ++w) t += sc.red[w][tid];
-        out[tid] = t;
+        for (int i = 0; i < per_q; ++i) t += sc.seg[qq * per_q + i][c];
+        out[q0 + qq][c] = t;
     }
     __syncthreads();
 }
 
-__device__ double decision_at(const Geom& g, const float2* y, const double th[4], Scratch& sc, double* mom) {
+__device__ __forceinline__ double decision_at(const Geom& g, const float2* y, const double th[4], Scratch& sc, double (*mom)[12]) {
+    const int gs = group_size(g);
+    for (int q0 = 0; q0 < g.k; q0 += gs) moments_group(g, y, th, q0, (g.k - q0 < gs) ? g.k - q0 : gs, false, sc, mom);
     double dsum = 0.0;
-    for (int q = 0; q < g.k; ++q) {
-        FreqD fq;
-        freq_derivs(g, q, th, fq);
-        moments(g, y + (size_t)q * g.mc * g.ms, cycles_to_fixed(fq.fr), cycles_to_fixed(fq.fd), false, sc, mom);
-        dsum += mom[0] * mom[0] + mom[1] * mom[1];
-    }
+    for (int q = 0; q < g.k; ++q) dsum += mom[q][0] * mom[q][0] + mom[q][1] * mom[q][1];
     return dsum;
 }
 
@@ -242,6 +285,7 @@ __global__ __launch_bounds__(kThreads) void refine_kernel(Geom g, GridP gp, cons
                                                          double* __restrict__ theta_out) {
     __shared__ Scratch sc;
     __shared__ double mom[kMaxRx][12];
+    __shared__ double mom2[kMaxRx][12];
     __shared__ double sh_step[4];
     const int tid = threadIdx.x;
     int64_t idx = cells[blockIdx.x];
@@ -255,71 +299,89 @@ __global__ __launch_bounds__(kThreads) void refine_kernel(Geom g, GridP gp, cons
                            gp.lo[3] + ivy * gp.step[3]};
     const double* h = gp.step;
     double z[4] = {0, 0, 0, 0};
-    double d_cur = decision_at(g, y, th0, sc, mom[0]);
+    double d_cur = decision_at(g, y, th0, sc, mom2);
     const double tp = 6.283185307179586;
     for (int it = 0; it < max_iter; ++it) {
         double th[4];
+#pragma unroll
         for (int a = 0; a < 4; ++a) th[a] = th0[a] + z[a] * h[a];
-        for (int q = 0; q < g.k; ++q) {
-            FreqD fq;
-            freq_derivs(g, q, th, fq);
-            moments(g, y + (size_t)q * g.mc * g.ms, cycles_to_fixed(fq.fr), cycles_to_fixed(fq.fd), true, sc,
-                    mom[q]);
+        {
+            const int gs = group_size(g);
+            for (int q0 = 0; q0 < g.k; q0 += gs)
+                moments_group(g, y, th, q0, (g.k - q0 < gs) ? g.k - q0 : gs, true, sc, mom);
         }
         if (tid == 0) {
             double grad[4] = {0, 0, 0, 0}, hess[4][4];
+#pragma unroll
             for (int a = 0; a < 4; ++a)
+#pragma unroll
                 for (int b = 0; b < 4; ++b) hess[a][b] = 0.0;
             for (int q = 0; q < g.k; ++q) {
-                FreqD f;
-                freq_derivs(g, q, th, f);
+                FreqC f;
+                freq_compact(g, q, th, f);
                 const double* mo = mom[q];
                 double dcr[4], dci[4];
+#pragma unroll
                 for (int a = 0; a < 4; ++a) {
-                    const double tr = f.gr[a] * mo[2] + f.gd[a] * mo[4];
-                    const double ti = f.gr[a] * mo[3] + f.gd[a] * mo[5];
+                    const double tr = gr_at(f, a) * mo[2] + gd_at(f, a) * mo[4];
+                    const double ti = gr_at(f, a) * mo[3] + gd_at(f, a) * mo[5];
                     dcr[a] = tp * ti;        // -j 2 pi (tr + j ti)
                     dci[a] = -tp * tr;
                 }
                 const double cr = mo[0], ci = mo[1];
+#pragma unroll
                 for (int a = 0; a < 4; ++a) {
                     grad[a] += 2.0 * (cr * dcr[a] + ci * dci[a]);
-                    for (int b = 0; b < 4; ++b) {
-                        const double k20 = f.gr[a] * f.gr[b], k11 = f.gr[a] * f.gd[b] + f.gd[a] * f.gr[b];
-                        const double k02 = f.gd[a] * f.gd[b];
+#pragma unroll
+                    for (int b = a; b < 4; ++b) {
+                        const double k20 = gr_at(f, a) * gr_at(f, b);
+                        const double k11 = gr_at(f, a) * gd_at(f, b) + gd_at(f, a) * gr_at(f, b);
+                        const double k02 = gd_at(f, a) * gd_at(f, b);
                         const double pr = k20 * mo[6] + k11 * mo[8] + k02 * mo[10];
                         const double pi = k20 * mo[7] + k11 * mo[9] + k02 * mo[11];
-                        const double sr = f.hr[a][b] * mo[2] + f.hd[a][b] * mo[4];
-                        const double si = f.hr[a][b] * mo[3] + f.hd[a][b] * mo[5];
+                        const double sr = hr_at(f, a, b) * mo[2] + hd_at(f, a, b) * mo[4];
+                        const double si = hr_at(f, a, b) * mo[3] + hd_at(f, a, b) * mo[5];
                         const double d2r = -tp * tp * pr + tp * si;     // -tp^2 (pr + j pi) - j tp (sr + j si)
                         const double d2i = -tp * tp * pi - tp * sr;
                         hess[a][b] += 2.0 * (dcr[a] * dcr[b] + dci[a] * dci[b] + cr * d2r + ci * d2i);
                     }
                 }
             }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < a; ++b) hess[a][b] = hess[b][a];
             double gz[4], hz[4][4], vec[4][4];
+#pragma unroll
             for (int a = 0; a < 4; ++a) {
                 gz[a] = (h[a] > 0.0) ? grad[a] * h[a] : 0.0;
+#pragma unroll
                 for (int b = 0; b < 4; ++b) hz[a][b] = hess[a][b] * h[a] * h[b];
             }
             jacobi4(hz, vec);
             double lmax = 0.0;
+#pragma unroll
             for (int a = 0; a < 4; ++a) lmax = fmax(lmax, fabs(hz[a][a]));
             const double floor_l = 1e-12 * fmax(lmax, 1e-300);
             double coef[4];
+#pragma unroll
             for (int i = 0; i < 4; ++i) {
                 double p = 0.0;
+#pragma unroll
                 for (int a = 0; a < 4; ++a) p += vec[a][i] * gz[a];
                 coef[i] = p / fmax(fabs(hz[i][i]), floor_l);
             }
+#pragma unroll
             for (int a = 0; a < 4; ++a) {
                 double s = 0.0;
+#pragma unroll
                 for (int i = 0; i < 4; ++i) s += vec[a][i] * coef[i];
                 sh_step[a] = (h[a] > 0.0) ? s : 0.0;
             }
         }
         __syncthreads();
         double step[4], smax = 0.0;
+#pragma unroll
         for (int a = 0; a < 4; ++a) {
             step[a] = sh_step[a];
             smax = fmax(smax, fabs(step[a]));
@@ -327,19 +389,23 @@ __global__ __launch_bounds__(kThreads) void refine_kernel(Geom g, GridP gp, cons
         if (smax < kTol) break;
         bool accepted = false;
         double cand[4], d_new = 0.0;
-        for (int tries = 0; tries < 31; ++tries) {
+        for (int tries = 0; tries < 16; ++tries) {
+#pragma unroll
             for (int a = 0; a < 4; ++a) cand[a] = fmin(1.0, fmax(-1.0, z[a] + step[a]));
             double thc[4];
+#pragma unroll
             for (int a = 0; a < 4; ++a) thc[a] = th0[a] + cand[a] * h[a];
-            d_new = decision_at(g, y, thc, sc, mom[0]);
+            d_new = decision_at(g, y, thc, sc, mom2);
             if (d_new >= d_cur) {
                 accepted = true;
                 break;
             }
+#pragma unroll
             for (int a = 0; a < 4; ++a) step[a] *= 0.5;
         }
         if (!accepted) break;
         double move = 0.0;
+#pragma unroll
         for (int a = 0; a < 4; ++a) {
             move = fmax(move, fabs(cand[a] - z[a]));
             z[a] = cand[a];
@@ -348,6 +414,7 @@ __global__ __launch_bounds__(kThreads) void refine_kernel(Geom g, GridP gp, cons
         if (move < kTol) break;
     }
     if (tid == 0)
+#pragma unroll
         for (int a = 0; a < 4; ++a) theta_out[(size_t)blockIdx.x * 4 + a] = th0[a] + z[a] * h[a];
 }
 
