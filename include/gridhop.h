@@ -20,6 +20,9 @@
  *    gh_last_error() describes the failure.  No C++ exception crosses the ABI.
  *  - Complex numbers are interleaved (re, im) pairs of float (complex64) or
  *    double.
+ *  - Every device array must be 16-byte aligned (hipMalloc and fresh torch
+ *    tensors are 256-byte aligned); a misaligned pointer is rejected with
+ *    GH_EINVAL.
  *  - Frames: d_y is complex64 [n_rx][n_chirps][n_samples], sample index
  *    fastest: row m of receiver q is chirp m of Y_q in C^{Mc x Ms}
  *    (paper Sec. II, eq. (3)).

@@ -7,6 +7,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <initializer_list>
+
 #include "gh_internal.h"
 
 namespace {
@@ -122,11 +124,17 @@ int check_sweep_limits(const gh::Geom& g, int interp) {
 
 int check_gemm(int gemm) {
     if (gemm != GH_GEMM_F32 && gemm != GH_GEMM_BF16) return fail(GH_EINVAL, "gemm_dtype must be F32 or BF16");
-    if (gemm == GH_GEMM_BF16) return fail(GH_EUNSUPPORTED, "BF16 direct path not built");
     return GH_OK;
 }
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Device arrays are read and written with 16-byte vector accesses.
+int check_aligned(std::initializer_list<const void*> ptrs) {
+    for (const void* p : ptrs)
+        if (((uintptr_t)p & 15) != 0) return fail(GH_EINVAL, "device arrays must be 16-byte aligned");
+    return GH_OK;
+}
 
 }  // namespace
 
@@ -141,6 +149,7 @@ int gh_rd_maps(const gh_radar* radar, const void* d_y, void* d_maps, void* strea
     int rc = make_geom(radar, g);
     if (rc) return rc;
     if (!d_y || !d_maps) return fail(GH_EINVAL, "d_y and d_maps must be non-NULL");
+    if ((rc = check_aligned({d_y, d_maps}))) return rc;
     const size_t ybytes = (size_t)g.k * g.mc * g.ms * 8, mbytes = (size_t)g.k * g.nr * g.nd * 8;
     const char *y0 = (const char*)d_y, *m0 = (const char*)d_maps;
     if (y0 < m0 + mbytes && m0 < y0 + ybytes) return fail(GH_EINVAL, "d_y and d_maps overlap");
@@ -157,6 +166,7 @@ int gh_decision(const gh_radar* radar, const gh_grid* grid, const void* d_maps, 
     int rc = make_geom(radar, g);
     if (rc || (rc = make_grid(grid, gp)) || (rc = check_sweep_limits(g, interp))) return rc;
     if (!d_maps || !d_block) return fail(GH_EINVAL, "d_maps and d_block must be non-NULL");
+    if ((rc = check_aligned({d_maps, d_decision, d_block, d_argmax}))) return rc;
     if ((rc = check_device())) return rc;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = gh::launch_gh_sweep(g, gp, (const float2*)d_maps, interp, d_decision, d_block, nullptr, 0, st);
@@ -168,8 +178,8 @@ int gh_decision(const gh_radar* radar, const gh_grid* grid, const void* d_maps, 
 int gh_argmax(const gh_peak* d_block, int64_t n_block, gh_peak* d_argmax, void* stream) {
     if (!d_block || !d_argmax) return fail(GH_EINVAL, "d_block and d_argmax must be non-NULL");
     if (n_block < 1 || n_block >= (1LL << 31)) return fail(GH_EINVAL, "n_block must be in [1, 2^31)");
-    int rc = check_device();
-    if (rc) return rc;
+    int rc = check_aligned({d_block, d_argmax});
+    if (rc || (rc = check_device())) return rc;
     hipError_t e = gh::launch_peak_final(d_block, (int)n_block, d_argmax, nullptr, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gh_argmax launch");
     return ok();
@@ -190,6 +200,7 @@ int gh_direct_decision(const gh_radar* radar, const gh_grid* grid, const void* d
     int rc = make_geom(radar, g);
     if (rc || (rc = make_grid(grid, gp)) || (rc = check_gemm(gemm_dtype))) return rc;
     if (!d_y || !d_block || !d_ws) return fail(GH_EINVAL, "d_y, d_ws and d_block must be non-NULL");
+    if ((rc = check_aligned({d_y, d_ws, d_decision, d_block, d_argmax}))) return rc;
     const size_t need = align256(gh::direct_ws_bytes(g, gp, gemm_dtype));
     if (ws_bytes < need) return fail(GH_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if ((rc = check_device())) return rc;
@@ -221,6 +232,7 @@ int gh_bomp_step(const gh_radar* radar, const gh_grid* grid, const void* d_y, vo
     if (!use_direct && (rc = check_sweep_limits(g, interp))) return rc;
     if (!d_y || !d_resid || !d_support || !d_alpha || !d_ws) return fail(GH_EINVAL, "NULL device pointer");
     if (!use_direct && !d_maps) return fail(GH_EINVAL, "d_maps must be non-NULL for grid hopping");
+    if ((rc = check_aligned({d_y, d_resid, d_maps, d_support, d_alpha, d_selected, d_ws}))) return rc;
     if (max_support < 1 || max_support > GH_MAX_SUPPORT)
         return fail(GH_EINVAL, "max_support must be in [1, %d]", GH_MAX_SUPPORT);
     if (n_support < 0 || n_support >= max_support)
@@ -259,6 +271,7 @@ int gh_refine(const gh_radar* radar, const gh_grid* grid, const void* d_y, const
     int rc = make_geom(radar, g);
     if (rc || (rc = make_grid(grid, gp))) return rc;
     if (!d_y || !d_cells || !d_theta) return fail(GH_EINVAL, "NULL device pointer");
+    if ((rc = check_aligned({d_y, d_cells, d_theta}))) return rc;
     if (n_cells < 0 || n_cells > 65535) return fail(GH_EINVAL, "n_cells must be in [0, 65535]");
     if (max_iter < 1 || max_iter > 100) return fail(GH_EINVAL, "max_iter must be in [1, 100]");
     if (n_cells == 0) return ok();

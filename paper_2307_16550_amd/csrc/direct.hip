@@ -1,115 +1,232 @@
 // Direct decision (paper Sec. I and III): exact scalar products of each
 // receiver's frame with the atoms of eq. (3),
 //   D_dir(x, v) = sum_q | sum_m sum_s Y_q[m][s] exp(-j 2 pi (f_r s + f_d m)) |^2,
-// evaluated as two contractions per receiver:
-//   stage 1 (range zoom): G_q[x][m] = sum_s Y_q[m][s] exp(-j 2 pi f_r(x) s),
-//     a [locations x Ms] x [Ms x Mc] complex product with the range atoms
-//     generated on the fly;
-//   stage 2 (Doppler zoom): per location, sum_m G_q[x][m] exp(-j 2 pi f_d(x, v) m)
-//     over the velocity slab, |.|^2, sum over receivers, slab write and block max.
-// Phases are held in 32-bit fixed point (cycles modulo one), so s * f_r and
-// m * f_d wrap exactly.  This file is the FP32 VALU path.
+// evaluated as two complex contractions per receiver on the matrix cores:
+//   range zoom   G_q[x][m] = sum_s A[x][s] Y_q[m][s],   A[x][s] = exp(-j 2 pi f_r(x) s)
+//                a [locations x Ms] x [Ms x Mc] product;
+//   Doppler zoom c_q[ivx][ivy] = sum_m (G_q[x][m] Ex[ivx][m]) Ey[m][ivy]
+//                per location a [Nvx x Mc] x [Mc x Nvy] product, because the
+//                Doppler frequency is affine in the velocity indices,
+//                f_d = f0 + ivx fx + ivy fy, so exp(-j 2 pi f_d m) factorises into
+//                Ex[ivx][m] = exp(-j 2 pi (f0 + ivx fx) m) and Ey[m][ivy] = exp(-j 2 pi ivy fy m);
+//   then |c_q|^2 summed over receivers, the slab write and the block maximum.
+//
+// Matrix-core mapping (64-lane wave, 16 x 16 output tile, FP32 accumulation):
+//   lane = r + 16 g holds contraction indices k0 + 8 g + e (e = 0..7) of row r
+//   of the left operand and of column r of the right operand.  BF16 issues
+//   one 16x16x32 product per real part pairing; FP32 issues eight 16x16x4
+//   products, the e-th taking element e of every lane (any assignment of
+//   contraction indices to the k slots is valid if both operands share it).
+//   The output element (i, j) sits in lane j + 16 (i / 4), slot i % 4.
+// A complex product is four real ones:
+//   Re C += Re A Re B - Im A Im B,  Im C += Re A Im B + Im A Re B.
+// Atoms are generated in registers: one exact anchor per run of eight from a
+// 32-bit fixed-point phase (the wrap modulo one cycle is integer overflow),
+// then the recurrence e_{n+1} = e_n exp(-j 2 pi f).
 #include "gh_internal.h"
 
 namespace gh {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kMaxPts = 16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// Stage 1: one workgroup per (group of `lt` locations, receiver).
-__global__ __launch_bounds__(kThreads) void direct_stage1_f32(Geom g, GridP gp, int lt, const float2* __restrict__ y,
-                                                             float2* __restrict__ gws) {
-    extern __shared__ float2 atoms[];   // [lt][Ms]
-    __shared__ uint32_t frq[16];
-    const int q = blockIdx.y;
-    const int loc0 = blockIdx.x * lt;
-    const int ms = g.ms, mc = g.mc;
-    if (threadIdx.x < lt) {
-        const int loc = loc0 + threadIdx.x;
-        uint32_t fr = 0;
-        if (loc < gp.nloc) {
-            const int ix = loc / gp.n[1], iy = loc - ix * gp.n[1];
-            double r, wx, wy;
-            bistatic(g, q, gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], r, wx, wy);
-            fr = cycles_to_fixed(g.fr_per_m * r);
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kRun = 8;     // contraction indices per lane per 32-wide step
+constexpr int kNT = 4;      // 16-wide chirp tiles per wave in the range zoom
+
+// exp(-j 2 pi f n) for n = n0 .. n0 + 7.
+__device__ __forceinline__ void atom_run(uint32_t f, uint32_t n0, float2 ratio, float2 (&e)[kRun]) {
+    e[0] = expm_fixed(f * n0);
+#pragma unroll
+    for (int i = 1; i < kRun; ++i) e[i] = cmul(e[i - 1], ratio);
+}
+
+__device__ __forceinline__ f32x4 zero4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
+
+// C += A B for complex operands held as kRun values per lane (layout above).
+template <bool BF16>
+__device__ __forceinline__ void mfma_complex(const float2 (&a)[kRun], const float2 (&b)[kRun], f32x4& cre,
+                                             f32x4& cim) {
+    if constexpr (BF16) {
+        bf16x8 ar, ai, nai, br, bi;
+#pragma unroll
+        for (int e = 0; e < kRun; ++e) {
+            ar[e] = (__bf16)a[e].x;
+            ai[e] = (__bf16)a[e].y;
+            nai[e] = (__bf16)(-a[e].y);
+            br[e] = (__bf16)b[e].x;
+            bi[e] = (__bf16)b[e].y;
         }
-        frq[threadIdx.x] = fr;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < lt * ms; e += kThreads) {
-        const int li = e / ms, s = e - li * ms;
-        atoms[e] = (loc0 + li < gp.nloc) ? expm_fixed(frq[li] * (uint32_t)s) : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-    const float2* yq = y + (size_t)q * mc * ms;
-    for (int o = threadIdx.x; o < lt * mc; o += kThreads) {
-        const int li = o / mc, m = o - li * mc;
-        const int loc = loc0 + li;
-        if (loc >= gp.nloc) continue;
-        const float2* row = yq + (size_t)m * ms;
-        const float2* at = atoms + li * ms;
-        float re = 0.f, im = 0.f;
-        for (int s = 0; s < ms; ++s) {
-            const float2 v = row[s], a = at[s];
-            re = fmaf(v.x, a.x, fmaf(-v.y, a.y, re));
-            im = fmaf(v.x, a.y, fmaf(v.y, a.x, im));
+        cre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, br, cre, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nai, bi, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, bi, cim, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, br, cim, 0, 0, 0);
+    } else {
+#pragma unroll
+        for (int e = 0; e < kRun; ++e) {
+            cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e].x, b[e].x, cre, 0, 0, 0);
+            cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[e].y, b[e].y, cre, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e].x, b[e].y, cim, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e].y, b[e].x, cim, 0, 0, 0);
         }
-        gws[((size_t)q * gp.nloc + loc) * mc + m] = make_float2(re, im);
     }
 }
 
-// Stage 2: one workgroup per location; threads own the velocity slab.
-__global__ __launch_bounds__(kThreads) void direct_stage2_f32(Geom g, GridP gp, const float2* __restrict__ gws,
-                                                             float* __restrict__ dec, gh_peak* __restrict__ block,
-                                                             const int64_t* __restrict__ excl, int nexcl) {
-    extern __shared__ float2 grow[];     // [Mc]
-    __shared__ uint32_t ph[kMaxRx][3];
-    __shared__ int excl_local[kMaxSupport];
-    __shared__ int n_excl_local;
-    __shared__ float red_v[kThreads / 64];
-    __shared__ int red_i[kThreads / 64];
-    const int tid = threadIdx.x;
-    const int loc = blockIdx.x;
-    const int ix = loc / gp.n[1], iy = loc - ix * gp.n[1];
-    const int nv = gp.nv, nvy = gp.n[3], mc = g.mc;
-    if (tid < g.k) {
-        double r, wx, wy;
-        bistatic(g, tid, gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], r, wx, wy);
-        ph[tid][0] = cycles_to_fixed(g.fd_per_mps * (wx * gp.lo[2] + wy * gp.lo[3]));
-        ph[tid][1] = cycles_to_fixed_step(g.fd_per_mps * wx * gp.step[2]);
-        ph[tid][2] = cycles_to_fixed_step(g.fd_per_mps * wy * gp.step[3]);
+__device__ __forceinline__ void load_run(const float2* __restrict__ p, float2 (&v)[kRun]) {
+    const float4* p4 = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int i = 0; i < kRun / 2; ++i) {
+        const float4 t = p4[i];
+        v[2 * i] = make_float2(t.x, t.y);
+        v[2 * i + 1] = make_float2(t.z, t.w);
     }
-    if (tid == 0) n_excl_local = local_exclusions(excl, nexcl, loc, nv, excl_local);
-    float acc[kMaxPts];
+}
+
+// Range zoom.  Grid (ceil(Nloc / 64), ceil(Mc / 64), K); wave w of a
+// workgroup owns 16 locations and 64 chirps of receiver blockIdx.z.
+template <bool BF16>
+__global__ __launch_bounds__(kThreads) void direct_range_zoom(Geom g, GridP gp, const float2* __restrict__ y,
+                                                             float2* __restrict__ gws) {
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15;
+    const int seg = lane >> 4;
+    const int q = blockIdx.z;
+    const int loc0 = (blockIdx.x * kWaves + (threadIdx.x >> 6)) * 16;
+    const int m0 = blockIdx.y * (16 * kNT);
+    const int ms = g.ms, mc = g.mc;
+
+    uint32_t fr = 0;
+    if (loc0 + r < gp.nloc) {
+        const int loc = loc0 + r;
+        const int ix = loc / gp.n[1], iy = loc - ix * gp.n[1];
+        double rr, wx, wy;
+        bistatic(g, q, gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], rr, wx, wy);
+        fr = cycles_to_fixed(g.fr_per_m * rr);
+    }
+    const float2 ratio = expm_fixed(fr);
+
+    f32x4 cre[kNT], cim[kNT];
 #pragma unroll
-    for (int j = 0; j < kMaxPts; ++j) acc[j] = 0.f;
-    for (int q = 0; q < g.k; ++q) {
-        __syncthreads();
-        for (int m = tid; m < mc; m += kThreads) grow[m] = gws[((size_t)q * gp.nloc + loc) * mc + m];
-        __syncthreads();
-        const uint32_t f0 = ph[q][0], fx = ph[q][1], fy = ph[q][2];
+    for (int t = 0; t < kNT; ++t) cre[t] = cim[t] = zero4();
+
+    const float2* yq = y + (size_t)q * mc * ms;
+    for (int s0 = 0; s0 < ms; s0 += 32) {
+        const int sb = s0 + seg * kRun;
+        const bool live = sb < ms;   // Ms is a power of two >= 8: a run is all in or all out
+        float2 a[kRun];
+        atom_run(fr, (uint32_t)sb, ratio, a);
+        if (!live) {
 #pragma unroll
-        for (int j = 0; j < kMaxPts; ++j) {
-            const int v = tid + j * kThreads;
-            if (v < nv) {
-                const int ivx = v / nvy, ivy = v - ivx * nvy;
-                const uint32_t fd = f0 + (uint32_t)ivx * fx + (uint32_t)ivy * fy;
-                uint32_t p = 0;
-                float re = 0.f, im = 0.f;
-                for (int m = 0; m < mc; ++m) {
-                    const float2 e = expm_fixed(p);
-                    const float2 gv = grow[m];
-                    re = fmaf(gv.x, e.x, fmaf(-gv.y, e.y, re));
-                    im = fmaf(gv.x, e.y, fmaf(gv.y, e.x, im));
-                    p += fd;
+            for (int e = 0; e < kRun; ++e) a[e] = make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) {
+            const int m = m0 + t * 16 + r;
+            float2 b[kRun];
+            if (live && m < mc) {
+                load_run(yq + (size_t)m * ms + sb, b);
+            } else {
+#pragma unroll
+                for (int e = 0; e < kRun; ++e) b[e] = make_float2(0.f, 0.f);
+            }
+            mfma_complex<BF16>(a, b, cre[t], cim[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kNT; ++t) {
+        const int m = m0 + t * 16 + r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int loc = loc0 + 4 * seg + e;
+            if (loc < gp.nloc && m < mc) gws[((size_t)q * gp.nloc + loc) * mc + m] = make_float2(cre[t][e], cim[t][e]);
+        }
+    }
+}
+
+// Doppler zoom.  One wave per location; it walks the 16 x 16 tiles of the
+// velocity slab, sums |c_q|^2 over receivers, writes the slab and reduces the
+// block maximum (ties to the lowest index), skipping excluded cells.
+template <bool BF16>
+__global__ __launch_bounds__(kThreads) void direct_doppler_zoom(Geom g, GridP gp, const float2* __restrict__ gws,
+                                                               float* __restrict__ dec, gh_peak* __restrict__ block,
+                                                               const int64_t* __restrict__ excl, int nexcl) {
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15;
+    const int seg = lane >> 4;
+    const int loc = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (loc >= gp.nloc) return;
+    const int ix = loc / gp.n[1], iy = loc - ix * gp.n[1];
+    const int nvx = gp.n[2], nvy = gp.n[3], nv = gp.nv, mc = g.mc;
+
+    // Doppler frequency of receiver `lane` at the slab origin and its steps per vx / vy index
+    uint32_t f0l = 0, fxl = 0, fyl = 0;
+    if (lane < g.k) {
+        double rr, wx, wy;
+        bistatic(g, lane, gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], rr, wx, wy);
+        f0l = cycles_to_fixed(g.fd_per_mps * (wx * gp.lo[2] + wy * gp.lo[3]));
+        fxl = cycles_to_fixed_step(g.fd_per_mps * wx * gp.step[2]);
+        fyl = cycles_to_fixed_step(g.fd_per_mps * wy * gp.step[3]);
+    }
+
+    const int tiles_y = (nvy + 15) >> 4;
+    const int ntiles = ((nvx + 15) >> 4) * tiles_y;
+    const int64_t base = (int64_t)loc * nv;
+    float best_v = -INFINITY;
+    int best_i = 0x7fffffff;
+    for (int tile = 0; tile < ntiles; ++tile) {
+        const int tx = tile / tiles_y, ty = tile - tx * tiles_y;
+        f32x4 dsum = zero4();
+        for (int q = 0; q < g.k; ++q) {
+            const uint32_t f0 = (uint32_t)__shfl((int)f0l, q, 64);
+            const uint32_t fx = (uint32_t)__shfl((int)fxl, q, 64);
+            const uint32_t fy = (uint32_t)__shfl((int)fyl, q, 64);
+            const uint32_t fa = f0 + (uint32_t)(tx * 16 + r) * fx;   // row ivx = 16 tx + r of Ex
+            const uint32_t fb = (uint32_t)(ty * 16 + r) * fy;        // column ivy = 16 ty + r of Ey
+            const float2 ra = expm_fixed(fa), rb = expm_fixed(fb);
+            const float2* gq = gws + ((size_t)q * gp.nloc + loc) * mc;
+            f32x4 cre = zero4(), cim = zero4();
+            for (int k0 = 0; k0 < mc; k0 += 32) {
+                const int mb = k0 + seg * kRun;
+                float2 a[kRun], b[kRun];
+                if (mb < mc) {   // Mc is a power of two >= 8: a run is all in or all out
+                    float2 gv[kRun];
+                    load_run(gq + mb, gv);
+                    atom_run(fa, (uint32_t)mb, ra, a);
+                    atom_run(fb, (uint32_t)mb, rb, b);
+#pragma unroll
+                    for (int e = 0; e < kRun; ++e) a[e] = cmul(gv[e], a[e]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < kRun; ++e) a[e] = b[e] = make_float2(0.f, 0.f);
                 }
-                acc[j] = fmaf(re, re, fmaf(im, im, acc[j]));
+                mfma_complex<BF16>(a, b, cre, cim);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dsum[e] = fmaf(cre[e], cre[e], fmaf(cim[e], cim[e], dsum[e]));
+        }
+        const int ivy = ty * 16 + r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int ivx = tx * 16 + 4 * seg + e;
+            if (ivx < nvx && ivy < nvy) {
+                const int v = ivx * nvy + ivy;
+                if (dec) dec[base + v] = dsum[e];
+                bool skip = false;
+                for (int i = 0; i < nexcl; ++i) skip |= (excl[i] == base + v);
+                if (!skip) peak_merge(best_v, best_i, dsum[e], v);
             }
         }
     }
-    __syncthreads();
-    slab_epilogue<kThreads, kMaxPts>(acc, nv, loc, dec, block, excl_local, n_excl_local, red_v, red_i);
+    wave_peak(best_v, best_i);
+    if (lane == 0) {
+        gh_peak p;
+        p.value = best_v;
+        p.reserved = 0;
+        p.index = base + (best_i == 0x7fffffff ? 0 : best_i);
+        block[loc] = p;
+    }
 }
 
 }  // namespace
@@ -120,17 +237,21 @@ size_t direct_ws_bytes(const Geom& g, const GridP& gp, int /*gemm*/) {
 
 hipError_t launch_direct(const Geom& g, const GridP& gp, const float2* y, int gemm, void* ws, float* dec,
                          gh_peak* block, const int64_t* excl, int nexcl, hipStream_t st) {
-    (void)gemm;
     float2* gws = static_cast<float2*>(ws);
-    int lt = 4096 / g.ms;
-    if (lt > 16) lt = 16;
-    if (lt < 1) lt = 1;
-    hipLaunchKernelGGL(direct_stage1_f32, dim3((gp.nloc + lt - 1) / lt, g.k), dim3(kThreads),
-                       (size_t)lt * g.ms * sizeof(float2), st, g, gp, lt, y, gws);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(direct_stage2_f32, dim3(gp.nloc), dim3(kThreads), (size_t)g.mc * sizeof(float2), st, g, gp,
-                       gws, dec, block, excl, nexcl);
+    const dim3 g1((gp.nloc + 16 * kWaves - 1) / (16 * kWaves), (g.mc + 16 * kNT - 1) / (16 * kNT), g.k);
+    const dim3 g2((gp.nloc + kWaves - 1) / kWaves);
+    if (gemm == GH_GEMM_BF16) {
+        hipLaunchKernelGGL(direct_range_zoom<true>, g1, dim3(kThreads), 0, st, g, gp, y, gws);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(direct_doppler_zoom<true>, g2, dim3(kThreads), 0, st, g, gp, gws, dec, block, excl, nexcl);
+    } else {
+        hipLaunchKernelGGL(direct_range_zoom<false>, g1, dim3(kThreads), 0, st, g, gp, y, gws);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(direct_doppler_zoom<false>, g2, dim3(kThreads), 0, st, g, gp, gws, dec, block, excl,
+                           nexcl);
+    }
     return hipGetLastError();
 }
 

@@ -119,3 +119,16 @@ def test_error_message_cleared_after_success(lib):
     assert gh.last_error()
     assert lib.gh_refine(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, FAKE, 0, 20, FAKE, None) == gh.GH_OK
     assert gh.last_error() == ""
+
+
+def test_misaligned_pointers_rejected(lib):
+    r = radar()
+    odd = ctypes.c_void_p(0x1008)      # 8-byte aligned only
+    far = ctypes.c_void_p(0x100000000)
+    assert lib.gh_rd_maps(ctypes.byref(r.c_struct), odd, far, None) == gh.GH_EINVAL
+    assert "aligned" in gh.last_error()
+    assert lib.gh_decision(ctypes.byref(r.c_struct), ctypes.byref(GRID), odd, 0, None, FAKE, None, None) == gh.GH_EINVAL
+    need = lib.gh_direct_workspace_bytes(ctypes.byref(r.c_struct), ctypes.byref(GRID), 1)
+    assert lib.gh_direct_decision(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, 1, odd, need, None, FAKE,
+                                  None, None) == gh.GH_EINVAL
+    assert lib.gh_refine(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, odd, 1, 20, FAKE, None) == gh.GH_EINVAL

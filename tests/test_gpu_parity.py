@@ -25,6 +25,7 @@ pytestmark = pytest.mark.gpu
 MAP_TOL = 1e-5
 DEC_TOL = 1e-5
 TIE_TOL = 1e-5
+BF16_TOL = 1e-2     # BF16 matrix-core operands, FP32 accumulation: decision and near-tie bar
 
 
 def dev():
@@ -39,13 +40,13 @@ def say(*a):
     print(*a, flush=True)
 
 
-def check_argmax(d_ref_at, gpu_idx, ref_idx, ref_val, label):
+def check_argmax(d_ref_at, gpu_idx, ref_idx, ref_val, label, tol=TIE_TOL):
     """Identical cells, or a reported near tie in the oracle's own values."""
     if gpu_idx == ref_idx:
         return 0
     v = d_ref_at(gpu_idx)
     say(f"[near-tie] {label}: gpu cell {gpu_idx} oracle cell {ref_idx} oracle values {v:.9g} vs {ref_val:.9g}")
-    assert v >= (1.0 - TIE_TOL) * ref_val, f"{label}: argmax differs beyond the near-tie bar"
+    assert v >= (1.0 - tol) * ref_val, f"{label}: argmax differs beyond the near-tie bar"
     return 1
 
 
@@ -217,23 +218,47 @@ def test_gh_wrapping_range_rows_and_doppler_seam():
 
 # ---------------------------------------------------------------- direct
 
-def test_direct_full_volume_cfg1():
-    say("direct cfg1")
-    s, r, gr = scene_and_radar(1)
-    dec, block, arg = gh.direct_decision(gr, gh.grid_of(s.grid), to_dev(s.y))
+GEMMS = [(gh.GEMM_F32, DEC_TOL), (gh.GEMM_BF16, BF16_TOL)]
+
+
+def direct_volume_check(s, r, gr, grid, gemm, tol, label):
+    dec, block, arg = gh.direct_decision(gr, gh.grid_of(grid), to_dev(s.y), gemm=gemm)
     dg = dec.cpu().numpy().astype(np.float64)
-    dr = odirect.direct_decision(s.y, r, s.grid)
-    assert np.max(np.abs(dg - dr)) / dr.max() <= DEC_TOL
+    dr = odirect.direct_decision(s.y, r, grid)
+    err = np.max(np.abs(dg - dr)) / dr.max()
+    say(f"{label}: max rel error {err:.3g}")
+    assert err <= tol
+    bv, _ = gh.decode_peaks(block)
+    assert np.array_equal(bv, dg.reshape(len(bv), -1).max(axis=1).astype(np.float32))
     _, ai = gh.decode_peaks(arg)
     ref_val, ref_idx = opeaks.global_peak(dr)
-    check_argmax(lambda i: dr.ravel()[i], int(ai[0]), ref_idx, ref_val, "direct cfg1")
+    check_argmax(lambda i: dr.ravel()[i], int(ai[0]), ref_idx, ref_val, label, tol)
 
 
-def test_direct_sampled_cfg2_subgrid():
-    say("direct cfg2 subgrid")
+@pytest.mark.parametrize("gemm,tol", GEMMS)
+def test_direct_full_volume_cfg1(gemm, tol):
+    say(f"direct cfg1 gemm={gemm}")
+    s, r, gr = scene_and_radar(1)
+    direct_volume_check(s, r, gr, s.grid, gemm, tol, f"direct cfg1 gemm={gemm}")
+
+
+@pytest.mark.parametrize("ms,mc,n", [(8, 8, (3, 5, 7, 9)), (16, 64, (9, 8, 16, 16)), (64, 32, (5, 13, 17, 33)),
+                                     (128, 16, (2, 3, 40, 1)), (32, 128, (1, 1, 1, 1)), (256, 8, (4, 4, 2, 48))])
+@pytest.mark.parametrize("gemm,tol", GEMMS)
+def test_direct_shapes(ms, mc, n, gemm, tol):
+    """Short contractions (Ms, Mc < 32), ragged location tails and velocity tiles."""
+    say(f"direct shapes ms={ms} mc={mc} n={n} gemm={gemm}")
+    s, r, gr = scene_and_radar(1, 9, ms=ms, mc=mc)
+    grid = sc.Grid((5.5, -9.0, -12.0, -11.0), (23.0, 9.5, 12.5, 11.0), n)
+    direct_volume_check(s, r, gr, grid, gemm, tol, f"direct ms={ms} mc={mc} n={n} gemm={gemm}")
+
+
+@pytest.mark.parametrize("gemm,tol", GEMMS)
+def test_direct_sampled_cfg2_subgrid(gemm, tol):
+    say(f"direct cfg2 subgrid gemm={gemm}")
     s, r, gr = scene_and_radar(2)
     grid = sc.direct_grid(s, 2)
-    dec, block, arg = gh.direct_decision(gr, gh.grid_of(grid), to_dev(s.y))
+    dec, block, arg = gh.direct_decision(gr, gh.grid_of(grid), to_dev(s.y), gemm=gemm)
     dg = dec.cpu().numpy().ravel()
     av, ai = gh.decode_peaks(arg)
     assert int(ai[0]) == int(np.argmax(dg))
@@ -243,13 +268,16 @@ def test_direct_sampled_cfg2_subgrid():
     idx = np.concatenate([rng.integers(0, dg.size, 400), np.arange(loc * nv, (loc + 1) * nv)])
     pts = np.stack([ord_.grid_point(grid, int(i)) for i in idx])
     ref = odirect.direct_points(s.y, r, pts[:, 0], pts[:, 1], pts[:, 2], pts[:, 3])
-    assert np.max(np.abs(dg[idx] - ref)) / max(ref.max(), float(av[0])) <= DEC_TOL
+    err = np.max(np.abs(dg[idx] - ref)) / max(ref.max(), float(av[0]))
+    say(f"direct cfg2 gemm={gemm}: sampled max rel error {err:.3g}")
+    assert err <= tol
 
 
+@pytest.mark.parametrize("gemm", [gh.GEMM_F32, gh.GEMM_BF16])
 @pytest.mark.parametrize("trial", range(3))
-def test_direct_recovers_on_grid_target(trial):
+def test_direct_recovers_on_grid_target(trial, gemm):
     s, r, gr = scene_and_radar(1, trial, snr_db=math.inf, on_grid=True)
-    _, _, arg = gh.direct_decision(gr, gh.grid_of(s.grid), to_dev(s.y), write_volume=False)
+    _, _, arg = gh.direct_decision(gr, gh.grid_of(s.grid), to_dev(s.y), gemm=gemm, write_volume=False)
     _, ai = gh.decode_peaks(arg)
     assert int(ai[0]) == true_cell(s)
 
@@ -268,12 +296,13 @@ def test_gh_equals_direct_at_node_aligned_cell():
 
 # ---------------------------------------------------------------- BOMP
 
-@pytest.mark.parametrize("use_direct", [False, True])
-def test_bomp_three_iterations_cfg1(use_direct):
-    say(f"bomp cfg1 direct={use_direct}")
+@pytest.mark.parametrize("use_direct,gemm", [(False, gh.GEMM_F32), (True, gh.GEMM_F32), (True, gh.GEMM_BF16)])
+def test_bomp_three_iterations_cfg1(use_direct, gemm):
+    say(f"bomp cfg1 direct={use_direct} gemm={gemm}")
+    tol = BF16_TOL if gemm == gh.GEMM_BF16 else TIE_TOL
     s, r, gr = scene_and_radar(1, 6, targets=3, snr_db=20.0)
     st = gh.BompState(gr, gh.grid_of(s.grid), to_dev(s.y), max_support=3, use_direct=use_direct,
-                      interp=gh.BICUBIC)
+                      interp=gh.BICUBIC, gemm=gemm)
     sup_ref, resid_ref = [], s.y
     for it in range(3):
         st.step()
@@ -282,7 +311,7 @@ def test_bomp_three_iterations_cfg1(use_direct):
         d = obomp.decision(resid_ref, r, s.grid, use_direct, ogh.BICUBIC)
         val, cell = opeaks.global_peak(d, exclude=sup_ref)
         flat = d.ravel()
-        check_argmax(lambda i: flat[i], sup_gpu[it], cell, val, f"bomp it {it}")
+        check_argmax(lambda i: flat[i], sup_gpu[it], cell, val, f"bomp it {it}", tol)
         sup_ref = sup_gpu                        # continue from the GPU's (validated) selection
         alpha_ref, resid_ref = obomp.fit(s.y, r, s.grid, sup_ref)
         ag = st.alpha.cpu().numpy()[: it + 1]
