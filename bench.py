@@ -189,6 +189,7 @@ def main():
     darg = gh.peaks_tensor(1, dev)
     bomp = gh.BompState(radar, grid, y, max_support=BOMP_ITERS, use_direct=False, interp=interp)
     theta = torch.empty((BOMP_ITERS, 4), dtype=torch.float64, device=dev)
+    rws = torch.empty(gh.refine_workspace_bytes(radar, grid, BOMP_ITERS), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
     def ev():
@@ -216,7 +217,7 @@ def main():
         bomp.reset()
         for _ in range(BOMP_ITERS):
             bomp.step()
-        gh.refine(radar, grid, y, bomp.support, theta=theta)
+        gh.refine(radar, grid, y, bomp.support, theta=theta, ws=rws)
         if record:
             e[5].record(stream)
             marks.append(e)
@@ -234,6 +235,20 @@ def main():
         return float(np.mean([m[i].elapsed_time(m[j]) for m in marks])) * 1e-3
 
     t_maps, t_sweep, t_arg, t_dir, t_total = avg(0, 1), avg(1, 2), avg(2, 3), avg(3, 4), avg(0, 5)
+
+    # the direct decision with BF16 matrix-core operands, timed on its own (not part of the step)
+    ws_b = torch.empty(gh.direct_workspace_bytes(radar, dgrid, gh.GEMM_BF16), dtype=torch.uint8, device=dev)
+    ddec_b = torch.empty_like(ddec)
+    for _ in range(3):
+        gh.direct_decision(radar, dgrid, y, gemm=gh.GEMM_BF16, ws=ws_b, dec=ddec_b, block=dblock, want_argmax=False)
+    eb0, eb1 = ev(), ev()
+    eb0.record(stream)
+    for _ in range(10):
+        gh.direct_decision(radar, dgrid, y, gemm=gh.GEMM_BF16, ws=ws_b, dec=ddec_b, block=dblock, want_argmax=False)
+    eb1.record(stream)
+    torch.cuda.synchronize()
+    t_dir_bf16 = eb0.elapsed_time(eb1) * 1e-3 / 10
+    err_bf16 = float((ddec_b.double() - ddec.double()).abs().max() / ddec.double().max())
     ms_step = wall / args.steps * 1e3
     pts_step = (1 + BOMP_ITERS) * n_gh + n_dir
     sweep_bytes = 4 * n_gh + radar.k * radar.nr * radar.nd * 8 + 16 * nloc
@@ -266,8 +281,10 @@ def main():
         "gh_points_per_s": n_gh / (t_maps + t_sweep + t_arg),
         "gh_sweep_points_per_s": n_gh / t_sweep,
         "direct_points_per_s": n_dir / t_dir,
+        "direct_bf16_points_per_s": n_dir / t_dir_bf16,
+        "direct_bf16_max_rel_diff_vs_f32": err_bf16,
         "speedup_gh_over_direct_per_point": (n_gh / (t_maps + t_sweep + t_arg)) / (n_dir / t_dir),
-        "roofline": {"kernel": "gh_sweep_kernel<bilinear>" if interp == gh.BILINEAR else "gh_sweep_kernel<bicubic>",
+        "roofline": {"kernel": "gh_sweep_columns<bilinear>" if interp == gh.BILINEAR else "gh_sweep_columns<bicubic>",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": sweep_bytes,

@@ -179,15 +179,27 @@ int gh_bomp_step(const gh_radar *radar, const gh_grid *grid, const void *d_y, vo
                  int32_t n_support, int32_t max_support, void *d_alpha, gh_peak *d_selected,
                  void *d_ws, size_t ws_bytes, void *stream);
 
+/* Workspace of gh_refine in bytes for n_cells (1..65535) starting cells; 0 on
+ * invalid arguments (see gh_last_error). */
+size_t gh_refine_workspace_bytes(const gh_radar *radar, const gh_grid *grid, int32_t n_cells);
+
 /* Off-grid refinement of the direct decision (not in the paper): starting at
  * each cell (int64 linear grid index, device), maximise D_dir over continuous
  * (x, y, vx, vy) within one grid step per axis by Newton ascent with analytic
  * gradient and Hessian (eigenvalues replaced by -|lambda|, step halving until
- * the decision does not decrease, clamping to the box).  Stops when the move
- * is below 1e-7 grid steps or after max_iter (1..100) iterations.
- * d_theta: double [n_cells][4] out.  FP64 accumulation, fixed-point phases. */
+ * the decision does not decrease, at most 16 candidates, clamping to the box).
+ * Stops when every step component, or the accepted move, is below 1e-7 grid
+ * steps, or after max_iter (1..100) iterations.  An axis with one grid point
+ * is held.  d_ws: workspace of gh_refine_workspace_bytes() (barrier counters
+ * and partial moments; its contents need no initialisation; may be NULL when
+ * n_cells == 0, which enqueues nothing).
+ * d_theta: double [n_cells][4] out; NaN marks a cell whose cooperating
+ * workgroups failed to meet within a bounded wait (about a second; possible
+ * only when other work holds the device's compute units for that long).
+ * Moments accumulate in FP32 per chirp and FP64 beyond; fixed-point phases. */
 int gh_refine(const gh_radar *radar, const gh_grid *grid, const void *d_y, const int64_t *d_cells,
-              int32_t n_cells, int32_t max_iter, double *d_theta, void *stream);
+              int32_t n_cells, int32_t max_iter, void *d_ws, size_t ws_bytes, double *d_theta,
+              void *stream);
 
 #ifdef __cplusplus
 }

@@ -264,19 +264,35 @@ int gh_bomp_step(const gh_radar* radar, const gh_grid* grid, const void* d_y, vo
     return ok();
 }
 
+size_t gh_refine_workspace_bytes(const gh_radar* radar, const gh_grid* grid, int32_t n_cells) {
+    gh::Geom g;
+    gh::GridP gp;
+    if (make_geom(radar, g) || make_grid(grid, gp)) return 0;
+    if (n_cells < 1 || n_cells > 65535) {
+        fail(GH_EINVAL, "n_cells must be in [1, 65535]");
+        return 0;
+    }
+    ok();
+    return align256(gh::refine_ws_bytes(g, n_cells));
+}
+
 int gh_refine(const gh_radar* radar, const gh_grid* grid, const void* d_y, const int64_t* d_cells, int32_t n_cells,
-              int32_t max_iter, double* d_theta, void* stream) {
+              int32_t max_iter, void* d_ws, size_t ws_bytes, double* d_theta, void* stream) {
     gh::Geom g;
     gh::GridP gp;
     int rc = make_geom(radar, g);
     if (rc || (rc = make_grid(grid, gp))) return rc;
     if (!d_y || !d_cells || !d_theta) return fail(GH_EINVAL, "NULL device pointer");
-    if ((rc = check_aligned({d_y, d_cells, d_theta}))) return rc;
+    if ((rc = check_aligned({d_y, d_cells, d_ws, d_theta}))) return rc;
     if (n_cells < 0 || n_cells > 65535) return fail(GH_EINVAL, "n_cells must be in [0, 65535]");
     if (max_iter < 1 || max_iter > 100) return fail(GH_EINVAL, "max_iter must be in [1, 100]");
     if (n_cells == 0) return ok();
+    if (!d_ws) return fail(GH_EINVAL, "d_ws must be non-NULL");
+    const size_t need = align256(gh::refine_ws_bytes(g, n_cells));
+    if (ws_bytes < need) return fail(GH_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if ((rc = check_device())) return rc;
-    hipError_t e = gh::launch_refine(g, gp, (const float2*)d_y, d_cells, n_cells, max_iter, d_theta, (hipStream_t)stream);
+    hipError_t e = gh::launch_refine(g, gp, (const float2*)d_y, d_cells, n_cells, max_iter, d_ws, d_theta,
+                                     (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gh_refine launch");
     return ok();
 }

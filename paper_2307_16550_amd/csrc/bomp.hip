@@ -7,6 +7,8 @@
 //   Gram[t][u] = <A_u, A_t> = Dir(f_r,u - f_r,t; Ms) * Dir(f_d,u - f_d,t; Mc)
 //   with the Dirichlet sum Dir(d; M) = sum_{n<M} exp(j 2 pi d n) in closed form;
 //   residual Y_q - sum_t alpha_t A_q(theta_t).
+// The right-hand side is spread over workgroups of 8 chirps (separable atoms,
+// FP32 products over a chirp, FP64 from there on) and summed in a fixed order.
 #include "gh_internal.h"
 
 namespace gh {
@@ -31,62 +33,115 @@ __device__ dcplx dirichlet(double d, int m) {
     return {c * ratio, s * ratio};
 }
 
-__device__ __forceinline__ double block_sum(double v, double* red) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < kThreads / 64; ++w) t += red[w];
-    return t;
+constexpr int kRowsPerChunk = 8;          // chirps per workgroup of the right-hand side
+constexpr int kTabEntries = 4096;         // range phase factors per atom group (32 KiB)
+
+// Sensed frequencies (cycles per sample, per chirp) of grid cell idx at receiver q.
+__device__ __forceinline__ void cell_freqs(const Geom& g, const GridP& gp, int q, int64_t idx, double& fr, double& fd) {
+    const int ivy = (int)(idx % gp.n[3]);
+    idx /= gp.n[3];
+    const int ivx = (int)(idx % gp.n[2]);
+    idx /= gp.n[2];
+    const int iy = (int)(idx % gp.n[1]);
+    const int ix = (int)(idx / gp.n[1]);
+    double r, wx, wy;
+    bistatic(g, q, gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], r, wx, wy);
+    const double vx = gp.lo[2] + ivx * gp.step[2], vy = gp.lo[3] + ivy * gp.step[3];
+    fr = g.fr_per_m * r;
+    fd = g.fd_per_mps * (wx * vx + wy * vy);
 }
 
-// One workgroup per receiver: rhs, Gram, Cholesky solve.  Writes alpha
-// (complex64 [nsel][K]) and the fixed-point phases of the selected atoms.
-__global__ __launch_bounds__(kThreads) void bomp_fit_kernel(Geom g, GridP gp, const float2* __restrict__ y,
+// Right-hand side A^H Y_q over chirps [m0, m0 + 8) of receiver q for every atom,
+// using the separable atom: sum_m e_d[m] sum_s Y[m][s] e_r[s].  Writes the
+// partial sums part[q][chunk][t] (FP64).
+__global__ __launch_bounds__(kThreads) void bomp_rhs_kernel(Geom g, GridP gp, const float2* __restrict__ y,
                                                            const int64_t* __restrict__ support, int nsel,
+                                                           double2* __restrict__ part) {
+    __shared__ float2 er[kTabEntries];
+    __shared__ float2 ed[kMaxSupport][kRowsPerChunk];
+    __shared__ uint32_t frx[kMaxSupport], fdx[kMaxSupport];
+    __shared__ double2 red[kThreads / 64][kMaxSupport];
+    const int q = blockIdx.y, chunk = blockIdx.x;
+    const int m0 = chunk * kRowsPerChunk;
+    const int tid = threadIdx.x, ms = g.ms;
+    if (tid < nsel) {
+        double fr, fd;
+        cell_freqs(g, gp, q, support[tid], fr, fd);
+        frx[tid] = cycles_to_fixed(fr);
+        fdx[tid] = cycles_to_fixed(fd);
+    }
+    __syncthreads();
+    for (int e = tid; e < nsel * kRowsPerChunk; e += kThreads) {
+        const int t = e / kRowsPerChunk, r = e - t * kRowsPerChunk;
+        ed[t][r] = expm_fixed(fdx[t] * (uint32_t)(m0 + r));
+    }
+    const int tpr = kThreads / kRowsPerChunk;            // lanes per chirp
+    const int row = tid / tpr, lane = tid - row * tpr;
+    const float2* yr = y + ((size_t)q * g.mc + m0 + row) * ms;
+    const int group = kTabEntries / ms;                  // atoms per table fill
+    for (int t0 = 0; t0 < nsel; t0 += group) {
+        const int na = nsel - t0 < group ? nsel - t0 : group;
+        __syncthreads();
+        for (int e = tid; e < na * ms; e += kThreads) {
+            const int t = e >> g.log2_ms, s = e & (ms - 1);
+            er[e] = expm_fixed(frx[t0 + t] * (uint32_t)s);
+        }
+        __syncthreads();
+        for (int t = 0; t < na; ++t) {
+            float re = 0.f, im = 0.f;
+            for (int s = lane; s < ms; s += tpr) {
+                const float2 v = yr[s], e = er[t * ms + s];
+                re = fmaf(v.x, e.x, fmaf(-v.y, e.y, re));
+                im = fmaf(v.x, e.y, fmaf(v.y, e.x, im));
+            }
+            const float2 d = ed[t0 + t][row];
+            double pr = (double)re * d.x - (double)im * d.y;
+            double pi = (double)re * d.y + (double)im * d.x;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                pr += __shfl_xor(pr, off, 64);
+                pi += __shfl_xor(pi, off, 64);
+            }
+            if ((tid & 63) == 0) red[tid >> 6][t0 + t] = make_double2(pr, pi);
+        }
+    }
+    __syncthreads();
+    if (tid < nsel) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int w = 0; w < kThreads / 64; ++w) {
+            acc.x += red[w][tid].x;
+            acc.y += red[w][tid].y;
+        }
+        part[((size_t)q * (g.mc / kRowsPerChunk) + chunk) * kMaxSupport + tid] = acc;
+    }
+}
+
+// One workgroup per receiver: sums the right-hand side partials, Gram,
+// Cholesky solve.  Writes alpha (complex64 [nsel][K]) and the fixed-point
+// phases of the selected atoms.
+__global__ __launch_bounds__(kThreads) void bomp_fit_kernel(Geom g, GridP gp, const int64_t* __restrict__ support,
+                                                           int nsel, const double2* __restrict__ part,
                                                            float2* __restrict__ alpha, uint32_t* __restrict__ phases) {
     __shared__ double fr[kMaxSupport], fd[kMaxSupport];
     __shared__ uint32_t frx[kMaxSupport], fdx[kMaxSupport];
     __shared__ dcplx rhs[kMaxSupport];
     __shared__ dcplx gram[kMaxSupport][kMaxSupport];
-    __shared__ double red[kThreads / 64];
     const int q = blockIdx.x;
     const int tid = threadIdx.x;
     if (tid < nsel) {
-        int64_t idx = support[tid];
-        const int ivy = (int)(idx % gp.n[3]);
-        idx /= gp.n[3];
-        const int ivx = (int)(idx % gp.n[2]);
-        idx /= gp.n[2];
-        const int iy = (int)(idx % gp.n[1]);
-        const int ix = (int)(idx / gp.n[1]);
-        double r, wx, wy;
-        bistatic(g, q, gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], r, wx, wy);
-        const double vx = gp.lo[2] + ivx * gp.step[2], vy = gp.lo[3] + ivy * gp.step[3];
-        fr[tid] = g.fr_per_m * r;
-        fd[tid] = g.fd_per_mps * (wx * vx + wy * vy);
+        cell_freqs(g, gp, q, support[tid], fr[tid], fd[tid]);
         frx[tid] = cycles_to_fixed(fr[tid]);
         fdx[tid] = cycles_to_fixed(fd[tid]);
+        const int nchunk = g.mc / kRowsPerChunk;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int c = 0; c < nchunk; ++c) {
+            const double2 v = part[((size_t)q * nchunk + c) * kMaxSupport + tid];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        rhs[tid] = {acc.x, acc.y};
     }
     __syncthreads();
-    const float2* yq = y + (size_t)q * g.mc * g.ms;
-    const int n = g.mc * g.ms;
-    for (int t = 0; t < nsel; ++t) {
-        double re = 0.0, im = 0.0;
-        const uint32_t a = frx[t], b = fdx[t];
-        for (int e = tid; e < n; e += kThreads) {
-            const uint32_t m = (uint32_t)(e >> g.log2_ms), s = (uint32_t)(e & (g.ms - 1));
-            const float2 ex = expm_fixed(a * s + b * m);
-            const float2 v = yq[e];
-            re += (double)(v.x * ex.x - v.y * ex.y);
-            im += (double)(v.x * ex.y + v.y * ex.x);
-        }
-        re = block_sum(re, red);
-        im = block_sum(im, red);
-        if (tid == 0) rhs[t] = {re, im};
-    }
     for (int e = tid; e < nsel * nsel; e += kThreads) {
         const int t = e / nsel, u = e - t * nsel;
         gram[t][u] = dmul(dirichlet(fr[u] - fr[t], g.ms), dirichlet(fd[u] - fd[t], g.mc));
@@ -160,13 +215,21 @@ __global__ __launch_bounds__(kThreads) void bomp_residual_kernel(Geom g, const f
 
 }  // namespace
 
-size_t bomp_fit_ws_bytes(const Geom& g) { return (size_t)kMaxSupport * g.k * 2 * sizeof(uint32_t); }
+size_t bomp_fit_ws_bytes(const Geom& g) {
+    return (size_t)g.k * (g.mc / kRowsPerChunk) * kMaxSupport * sizeof(double2) +
+           (size_t)kMaxSupport * g.k * 2 * sizeof(uint32_t);
+}
 
 hipError_t launch_bomp_fit(const Geom& g, const GridP& gp, const float2* y, float2* resid, const int64_t* support,
                            int nsel, float2* alpha, void* ws, hipStream_t st) {
-    uint32_t* phases = static_cast<uint32_t*>(ws);
-    hipLaunchKernelGGL(bomp_fit_kernel, dim3(g.k), dim3(kThreads), 0, st, g, gp, y, support, nsel, alpha, phases);
+    double2* part = static_cast<double2*>(ws);
+    uint32_t* phases = reinterpret_cast<uint32_t*>(part + (size_t)g.k * (g.mc / kRowsPerChunk) * kMaxSupport);
+    hipLaunchKernelGGL(bomp_rhs_kernel, dim3(g.mc / kRowsPerChunk, g.k), dim3(kThreads), 0, st, g, gp, y, support,
+                       nsel, part);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bomp_fit_kernel, dim3(g.k), dim3(kThreads), 0, st, g, gp, support, nsel, part, alpha, phases);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int n = g.mc * g.ms;
     hipLaunchKernelGGL(bomp_residual_kernel, dim3((n + kThreads - 1) / kThreads, g.k), dim3(kThreads), 0, st, g, y,

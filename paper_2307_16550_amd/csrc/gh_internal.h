@@ -170,7 +170,8 @@ size_t bomp_fit_ws_bytes(const Geom& g);
 hipError_t launch_bomp_fit(const Geom& g, const GridP& gp, const float2* y, float2* resid,
                            const int64_t* support, int nsel, float2* alpha, void* ws, hipStream_t st);
 
+size_t refine_ws_bytes(const Geom& g, int ncells);
 hipError_t launch_refine(const Geom& g, const GridP& gp, const float2* y, const int64_t* cells, int ncells,
-                         int max_iter, double* theta, hipStream_t st);
+                         int max_iter, void* ws, double* theta, hipStream_t st);
 
 }  // namespace gh

@@ -18,6 +18,9 @@
 // -|lambda| (cyclic Jacobi, FP64); the ascent stops when every step component
 // is below 1e-7 steps; otherwise the step is halved until the decision does
 // not decrease (at most 16 candidates) and clamped to +-1 grid step.
+#include <stdlib.h>
+#include <string.h>
+
 #include "gh_internal.h"
 
 namespace gh {
@@ -280,27 +283,173 @@ __device__ __forceinline__ double decision_at(const Geom& g, const float2* y, co
     return dsum;
 }
 
-__global__ __launch_bounds__(kThreads) void refine_kernel(Geom g, GridP gp, const float2* __restrict__ y,
-                                                         const int64_t* __restrict__ cells, int max_iter,
-                                                         double* __restrict__ theta_out) {
-    __shared__ Scratch sc;
-    __shared__ double mom[kMaxRx][12];
-    __shared__ double mom2[kMaxRx][12];
-    __shared__ double sh_step[4];
-    const int tid = threadIdx.x;
-    int64_t idx = cells[blockIdx.x];
+// Contribution of receiver q to the gradient (4) and the upper triangle of
+// the Hessian (10, row-major a <= b) of D at theta, from its moments.
+__device__ __forceinline__ void newton_terms(const Geom& g, int q, const double th[4], const double* mo,
+                                             double out[14]) {
+    const double tp = 6.283185307179586;
+    FreqC f;
+    freq_compact(g, q, th, f);
+    double dcr[4], dci[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const double tr = gr_at(f, a) * mo[2] + gd_at(f, a) * mo[4];
+        const double ti = gr_at(f, a) * mo[3] + gd_at(f, a) * mo[5];
+        dcr[a] = tp * ti;        // -j 2 pi (tr + j ti)
+        dci[a] = -tp * tr;
+    }
+    const double cr = mo[0], ci = mo[1];
+    int k = 4;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        out[a] = 2.0 * (cr * dcr[a] + ci * dci[a]);
+#pragma unroll
+        for (int b = a; b < 4; ++b) {
+            const double k20 = gr_at(f, a) * gr_at(f, b);
+            const double k11 = gr_at(f, a) * gd_at(f, b) + gd_at(f, a) * gr_at(f, b);
+            const double k02 = gd_at(f, a) * gd_at(f, b);
+            const double pr = k20 * mo[6] + k11 * mo[8] + k02 * mo[10];
+            const double pi = k20 * mo[7] + k11 * mo[9] + k02 * mo[11];
+            const double sr = hr_at(f, a, b) * mo[2] + hd_at(f, a, b) * mo[4];
+            const double si = hr_at(f, a, b) * mo[3] + hd_at(f, a, b) * mo[5];
+            const double d2r = -tp * tp * pr + tp * si;     // -tp^2 (pr + j pi) - j tp (sr + j si)
+            const double d2i = -tp * tp * pi - tp * sr;
+            out[k++] = 2.0 * (dcr[a] * dcr[b] + dci[a] * dci[b] + cr * d2r + ci * d2i);
+        }
+    }
+}
+
+// Newton step in grid-step coordinates from the summed gradient and Hessian:
+// step = sum_i (e_i . g) / max(|lambda_i|, 1e-12 max|lambda|) e_i over the
+// eigenpairs of the scaled Hessian.  Where the Hessian is negative definite
+// with a moderate condition number this is (-H)^-1 g, solved by Cholesky;
+// otherwise by the cyclic Jacobi eigen-decomposition.
+__device__ __forceinline__ void newton_solve(const double t[14], const double h[4], double step[4]) {
+    double gz[4], hz[4][4];
+    int k = 4;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        gz[a] = (h[a] > 0.0) ? t[a] * h[a] : 0.0;
+#pragma unroll
+        for (int b = a; b < 4; ++b) {
+            hz[a][b] = t[k++] * h[a] * h[b];
+            hz[b][a] = hz[a][b];
+        }
+    }
+    // Cholesky of -H on the free axes (a held axis gets a unit row and no gradient)
+    double l[4][4], dmax = 0.0;
+    bool spd = true;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const bool fa = h[a] > 0.0, fb = h[b] > 0.0;
+            l[a][b] = (fa && fb) ? -hz[a][b] : (a == b ? 1.0 : 0.0);
+        }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) dmax = fmax(dmax, fabs(l[a][a]));
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        double d = l[j][j];
+#pragma unroll
+        for (int k2 = 0; k2 < j; ++k2) d -= l[j][k2] * l[j][k2];
+        spd = spd && d > 1e-10 * dmax;
+        const double ljj = sqrt(fmax(d, 1e-300));
+        l[j][j] = ljj;
+#pragma unroll
+        for (int i = j + 1; i < 4; ++i) {
+            double v = l[i][j];
+#pragma unroll
+            for (int k2 = 0; k2 < j; ++k2) v -= l[i][k2] * l[j][k2];
+            l[i][j] = v / ljj;
+        }
+    }
+    if (spd) {
+        double w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double v = gz[i];
+#pragma unroll
+            for (int k2 = 0; k2 < i; ++k2) v -= l[i][k2] * w[k2];
+            w[i] = v / l[i][i];
+        }
+#pragma unroll
+        for (int i = 3; i >= 0; --i) {
+            double v = w[i];
+#pragma unroll
+            for (int k2 = i + 1; k2 < 4; ++k2) v -= l[k2][i] * step[k2];
+            step[i] = v / l[i][i];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) step[a] = (h[a] > 0.0) ? step[a] : 0.0;
+        return;
+    }
+    double vec[4][4];
+    jacobi4(hz, vec);
+    double lmax = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) lmax = fmax(lmax, fabs(hz[a][a]));
+    const double floor_l = 1e-12 * fmax(lmax, 1e-300);
+    double coef[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double p = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) p += vec[a][i] * gz[a];
+        coef[i] = p / fmax(fabs(hz[i][i]), floor_l);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s += vec[a][i] * coef[i];
+        step[a] = (h[a] > 0.0) ? s : 0.0;
+    }
+}
+
+// Newton step from the moments of every receiver (one thread).
+__device__ __forceinline__ void newton_step(const Geom& g, const double th[4], const double h[4],
+                                            const double (*mom)[12], double step[4]) {
+    double t[14];
+#pragma unroll
+    for (int i = 0; i < 14; ++i) t[i] = 0.0;
+    for (int q = 0; q < g.k; ++q) {
+        double c[14];
+        newton_terms(g, q, th, mom[q], c);
+#pragma unroll
+        for (int i = 0; i < 14; ++i) t[i] += c[i];
+    }
+    newton_solve(t, h, step);
+}
+
+__device__ __forceinline__ void start_point(const GridP& gp, int64_t idx, double th0[4]) {
     const int ivy = (int)(idx % gp.n[3]);
     idx /= gp.n[3];
     const int ivx = (int)(idx % gp.n[2]);
     idx /= gp.n[2];
     const int iy = (int)(idx % gp.n[1]);
     const int ix = (int)(idx / gp.n[1]);
-    const double th0[4] = {gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], gp.lo[2] + ivx * gp.step[2],
-                           gp.lo[3] + ivy * gp.step[3]};
-    const double* h = gp.step;
+    th0[0] = gp.lo[0] + ix * gp.step[0];
+    th0[1] = gp.lo[1] + iy * gp.step[1];
+    th0[2] = gp.lo[2] + ivx * gp.step[2];
+    th0[3] = gp.lo[3] + ivy * gp.step[3];
+}
+
+// Single-workgroup refinement (one workgroup per cell; frames streamed from
+// memory).  Used when a cell's cluster would not fit on the device at once.
+__global__ __launch_bounds__(kThreads) void refine_single_kernel(Geom g, GridP gp, const float2* __restrict__ y,
+                                                                const int64_t* __restrict__ cells, int max_iter,
+                                                                double* __restrict__ theta_out) {
+    __shared__ Scratch sc;
+    __shared__ double mom[kMaxRx][12];
+    __shared__ double mom2[kMaxRx][12];
+    __shared__ double sh_step[4];
+    const int tid = threadIdx.x;
+    double th0[4];
+    start_point(gp, cells[blockIdx.x], th0);
+    const double h[4] = {gp.step[0], gp.step[1], gp.step[2], gp.step[3]};
     double z[4] = {0, 0, 0, 0};
     double d_cur = decision_at(g, y, th0, sc, mom2);
-    const double tp = 6.283185307179586;
     for (int it = 0; it < max_iter; ++it) {
         double th[4];
 #pragma unroll
@@ -310,75 +459,7 @@ __global__ __launch_bounds__(kThreads) void refine_kernel(Geom g, GridP gp, cons
             for (int q0 = 0; q0 < g.k; q0 += gs)
                 moments_group(g, y, th, q0, (g.k - q0 < gs) ? g.k - q0 : gs, true, sc, mom);
         }
-        if (tid == 0) {
-            double grad[4] = {0, 0, 0, 0}, hess[4][4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) hess[a][b] = 0.0;
-            for (int q = 0; q < g.k; ++q) {
-                FreqC f;
-                freq_compact(g, q, th, f);
-                const double* mo = mom[q];
-                double dcr[4], dci[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const double tr = gr_at(f, a) * mo[2] + gd_at(f, a) * mo[4];
-                    const double ti = gr_at(f, a) * mo[3] + gd_at(f, a) * mo[5];
-                    dcr[a] = tp * ti;        // -j 2 pi (tr + j ti)
-                    dci[a] = -tp * tr;
-                }
-                const double cr = mo[0], ci = mo[1];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    grad[a] += 2.0 * (cr * dcr[a] + ci * dci[a]);
-#pragma unroll
-                    for (int b = a; b < 4; ++b) {
-                        const double k20 = gr_at(f, a) * gr_at(f, b);
-                        const double k11 = gr_at(f, a) * gd_at(f, b) + gd_at(f, a) * gr_at(f, b);
-                        const double k02 = gd_at(f, a) * gd_at(f, b);
-                        const double pr = k20 * mo[6] + k11 * mo[8] + k02 * mo[10];
-                        const double pi = k20 * mo[7] + k11 * mo[9] + k02 * mo[11];
-                        const double sr = hr_at(f, a, b) * mo[2] + hd_at(f, a, b) * mo[4];
-                        const double si = hr_at(f, a, b) * mo[3] + hd_at(f, a, b) * mo[5];
-                        const double d2r = -tp * tp * pr + tp * si;     // -tp^2 (pr + j pi) - j tp (sr + j si)
-                        const double d2i = -tp * tp * pi - tp * sr;
-                        hess[a][b] += 2.0 * (dcr[a] * dcr[b] + dci[a] * dci[b] + cr * d2r + ci * d2i);
-                    }
-                }
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < a; ++b) hess[a][b] = hess[b][a];
-            double gz[4], hz[4][4], vec[4][4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                gz[a] = (h[a] > 0.0) ? grad[a] * h[a] : 0.0;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) hz[a][b] = hess[a][b] * h[a] * h[b];
-            }
-            jacobi4(hz, vec);
-            double lmax = 0.0;
-#pragma unroll
-            for (int a = 0; a < 4; ++a) lmax = fmax(lmax, fabs(hz[a][a]));
-            const double floor_l = 1e-12 * fmax(lmax, 1e-300);
-            double coef[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                double p = 0.0;
-#pragma unroll
-                for (int a = 0; a < 4; ++a) p += vec[a][i] * gz[a];
-                coef[i] = p / fmax(fabs(hz[i][i]), floor_l);
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                double s = 0.0;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) s += vec[a][i] * coef[i];
-                sh_step[a] = (h[a] > 0.0) ? s : 0.0;
-            }
-        }
+        if (tid == 0) newton_step(g, th, h, mom, sh_step);
         __syncthreads();
         double step[4], smax = 0.0;
 #pragma unroll
@@ -418,12 +499,466 @@ __global__ __launch_bounds__(kThreads) void refine_kernel(Geom g, GridP gp, cons
         for (int a = 0; a < 4; ++a) theta_out[(size_t)blockIdx.x * 4 + a] = th0[a] + z[a] * h[a];
 }
 
+// ---- cluster refinement ------------------------------------------------------
+// A cell's (receiver, chirp) rows are split over W workgroups ("the cluster")
+// of R rows each.  One pass evaluates all six moments at up to kCand points
+// (the line-search candidates z + step/2^i in the order they are tried, or the
+// start point): every workgroup reduces its rows of the frame to partial
+// moments per receiver, publishes them, meets the rest of the cluster at a
+// barrier in global memory and then sums all partials in one fixed order, so
+// every workgroup holds bit-identical moments and takes the same decisions (the
+// same sequence of passes).  The first acceptable candidate's moments give the
+// next Newton step without another pass; the accepted points are those of a
+// one-candidate-at-a-time line search.  A launch holds no more workgroups than
+// the device keeps resident at once (occupancy times compute units), so on a
+// device not shared with other work every workgroup of a cluster is resident
+// together; each barrier wait is bounded regardless (an expired wait aborts the
+// launch's cells, whose estimates are then NaN).
+
+constexpr int kCT = 512;             // threads of a cluster workgroup
+constexpr int kCand = 4;             // points per pass
+constexpr int kRowsMaxC = kCT / kCand;   // rows per workgroup (one thread per (point, row))
+constexpr int kRowsMinC = kCT / 64;      // at most 64 lanes per row
+constexpr int kWgsTarget = 32;       // preferred workgroups per cell
+constexpr int kErMax = 8192;         // range phase factors per pass (64 KB of LDS)
+constexpr int kSlotsMax = 4096;      // workgroups per launch (partial-buffer slots)
+constexpr unsigned kSpinLimit = 1u << 21;
+
+struct Cluster {
+    int rows_per_wg;   // R, a power of two (a divisor or a multiple of Mc)
+    int wgs;           // W = ceil(K Mc / R)
+    int slots;         // partial-buffer slots (workgroups of one launch)
+};
+
+struct ClusterShared {
+    float2 ed[kCand][kRowsMaxC];          // Doppler phase factor [point][row]
+    double2 a[kCand][3][kRowsMaxC];       // A_p [point][p][row]
+    double red[kCand][kRowsMaxC / 8][12]; // per-lane-group partial moments
+    double mom[kCand][kMaxRx][12];        // the cell's moments at each point of the pass
+    double cur[kMaxRx][12];               // moments at the current point
+    double terms[kMaxRx][14];             // per-receiver Newton terms
+    double tsum[14];
+    double th[kCand][4];
+    double cand[kCand][4];                // the points in grid-step coordinates
+    uint32_t fr[kCand][kMaxRx], fd[kCand][kMaxRx];
+    double step[4];
+    int ok;
+};
+
+// Cluster barrier: arrival count `target` on this cell's counter.  Bounded: a
+// wait that exceeds the spin limit, or sees the launch's abort flag, raises the
+// flag and returns false (every waiting workgroup then leaves).
+__device__ bool cell_barrier(unsigned* ctr, unsigned target, unsigned* abort_flag, int* ok_sh) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __threadfence();
+        atomicAdd(ctr, 1u);
+        unsigned spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                ++spins > kSpinLimit) {
+                atomicExch(abort_flag, 1u);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(4);
+        }
+        __threadfence();
+        *ok_sh = ok;
+    }
+    __syncthreads();
+    return *ok_sh != 0;
+}
+
+struct ClusterCtx {
+    int cell, part, slot0, r0, nrows, q_lo, nq;
+};
+
+// One pass at the points sh.th[0 .. npts): leaves all six moments of every
+// receiver at each point in sh.mom.  er: LDS table of range phase factors.
+__device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx& cx, const float2* __restrict__ y,
+                             float2* er, int npts, unsigned& pass, ClusterShared& sh, unsigned* ctr,
+                             unsigned* abort_flag, double* __restrict__ part) {
+    const int tid = threadIdx.x;
+    const int ms = g.ms, mc = g.mc, R = cl.rows_per_wg;
+    if (tid < npts * cx.nq) {
+        const int c = tid / cx.nq, i = tid - c * cx.nq;
+        FreqC f;
+        freq_compact(g, cx.q_lo + i, sh.th[c], f);
+        sh.fr[c][i] = cycles_to_fixed(f.fr);
+        sh.fd[c][i] = cycles_to_fixed(f.fd);
+    }
+    __syncthreads();
+    const int nte = cx.nq * ms;
+    for (int e = tid; e < npts * nte; e += kCT) {
+        const int c = e / nte, r = e - c * nte;
+        const int i = r >> g.log2_ms, s = r & (ms - 1);
+        er[e] = expm_fixed(sh.fr[c][i] * (uint32_t)s);
+    }
+    for (int e = tid; e < npts * cx.nrows; e += kCT) {
+        const int c = e / cx.nrows, r = e - c * cx.nrows;
+        const int gr = cx.r0 + r;
+        sh.ed[c][r] = expm_fixed(sh.fd[c][(gr >> g.log2_mc) - cx.q_lo] * (uint32_t)(gr & (mc - 1)));
+    }
+    __syncthreads();
+    // per row and point: A_p = sum_s s^p Y[row][s] e_r[s] (FP32 products and sums, tpr lanes per row)
+    {
+        const int tpr = kCT / R;
+        const int row = tid / tpr, lane = tid & (tpr - 1);
+        float acc[kCand][6];
+#pragma unroll
+        for (int c = 0; c < kCand; ++c)
+#pragma unroll
+            for (int i = 0; i < 6; ++i) acc[c][i] = 0.f;
+        if (row < cx.nrows) {
+            const float2* yr = y + (size_t)(cx.r0 + row) * ms;
+            const int eoff = (((cx.r0 + row) >> g.log2_mc) - cx.q_lo) * ms;
+            // eight independent loads in flight per lane, then their products
+            for (int s0 = lane; s0 < ms; s0 += 8 * tpr) {
+                float2 v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int s = s0 + k * tpr;
+                    v[k] = s < ms ? yr[s] : make_float2(0.f, 0.f);
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int s = s0 + k * tpr;
+                    if (s < ms) {
+                        const float fs = (float)s, fs2 = fs * fs;
+#pragma unroll
+                        for (int c = 0; c < kCand; ++c) {
+                            if (c < npts) {
+                                const float2 e = er[c * nte + eoff + s];
+                                const float re = fmaf(v[k].x, e.x, -v[k].y * e.y);
+                                const float im = fmaf(v[k].x, e.y, v[k].y * e.x);
+                                acc[c][0] += re;
+                                acc[c][1] += im;
+                                acc[c][2] = fmaf(re, fs, acc[c][2]);
+                                acc[c][3] = fmaf(im, fs, acc[c][3]);
+                                acc[c][4] = fmaf(re, fs2, acc[c][4]);
+                                acc[c][5] = fmaf(im, fs2, acc[c][5]);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        // level by level, so the shuffles of one level are independent
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            if (off < tpr) {
+#pragma unroll
+                for (int c = 0; c < kCand; ++c)
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) acc[c][i] += __shfl_xor(acc[c][i], off, 64);
+            }
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < kCand; ++c)
+#pragma unroll
+                for (int p = 0; p < 3; ++p) sh.a[c][p][row] = make_double2(acc[c][2 * p], acc[c][2 * p + 1]);
+        }
+    }
+    __syncthreads();
+    // per (point, row): Doppler factor and chirp weights, FP64 sums over each receiver's rows
+    {
+        const int c = tid / R, row = tid - c * R;       // kCand * R <= kCT
+        double acc[12];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) acc[i] = 0.0;
+        if (c < npts && row < cx.nrows) {
+            const float2 e = sh.ed[c][row];
+            const double dm = (double)((cx.r0 + row) & (mc - 1));
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const double2 a = sh.a[c][p][row];
+                const double re = a.x * e.x - a.y * e.y;
+                const double im = a.x * e.y + a.y * e.x;
+                if (p == 0) {
+                    acc[0] = re;
+                    acc[1] = im;
+                    acc[4] = re * dm;
+                    acc[5] = im * dm;
+                    acc[10] = re * dm * dm;
+                    acc[11] = im * dm * dm;
+                } else if (p == 1) {
+                    acc[2] = re;
+                    acc[3] = im;
+                    acc[8] = re * dm;
+                    acc[9] = im * dm;
+                } else {
+                    acc[6] = re;
+                    acc[7] = im;
+                }
+            }
+        }
+        const int seg = R < mc ? R : mc;               // rows of one receiver in this workgroup
+        const int gsz = seg < 64 ? seg : 64;           // of which one lane group of a wave
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            if (off < gsz) {
+#pragma unroll
+                for (int i = 0; i < 12; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
+            }
+        }
+        if (c < kCand && (row & (gsz - 1)) == 0) {
+#pragma unroll
+            for (int i = 0; i < 12; ++i) sh.red[c][row / gsz][i] = acc[i];
+        }
+        __syncthreads();
+        const int per = seg / gsz;                     // lane groups per receiver
+        const int par = (int)(pass & 1u);
+        for (int e = tid; e < npts * cx.nq * 12; e += kCT) {
+            const int cc = e / (cx.nq * 12), r = e - cc * (cx.nq * 12);
+            const int i = r / 12, k = r - i * 12;
+            double t = 0.0;
+            for (int j = 0; j < per; ++j) t += sh.red[cc][i * per + j][k];
+            part[((((size_t)par * cl.slots + cx.slot0 + cx.part) * kCand + cc) * kMaxRx + i) * 12 + k] = t;
+        }
+    }
+    const bool ok = cell_barrier(ctr + cx.cell, (pass + 1u) * (unsigned)cl.wgs, abort_flag, &sh.ok);
+    if (ok) {
+        const int par = (int)(pass & 1u);
+        const int per_q = R < mc ? mc / R : 1;         // workgroups holding one receiver
+        const int q_per = R > mc ? R / mc : 1;         // receivers held by one workgroup
+        for (int e = tid; e < npts * g.k * 12; e += kCT) {
+            const int c = e / (g.k * 12), r = e - c * (g.k * 12);
+            const int q = r / 12, k = r - q * 12;
+            double t = 0.0;
+            for (int j = 0; j < per_q; ++j) {
+                const int p = R < mc ? q * per_q + j : q / q_per;
+                const int i = R > mc ? q - p * q_per : 0;
+                t += part[((((size_t)par * cl.slots + cx.slot0 + p) * kCand + c) * kMaxRx + i) * 12 + k];
+            }
+            sh.mom[c][q][k] = t;
+        }
+    }
+    __syncthreads();
+    ++pass;
+    return ok;
+}
+
+__device__ __forceinline__ double point_value(const Geom& g, const double (*mom)[12]) {
+    double d = 0.0;
+    for (int q = 0; q < g.k; ++q) d += mom[q][0] * mom[q][0] + mom[q][1] * mom[q][1];
+    return d;
+}
+
+__global__ __launch_bounds__(kCT) void refine_cluster_kernel(Geom g, GridP gp, const float2* __restrict__ y,
+                                                            const int64_t* __restrict__ cells, int cell0,
+                                                            int max_iter, Cluster cl,
+                                                            double* __restrict__ theta_out, unsigned* ctr,
+                                                            unsigned* abort_flag, double* part) {
+    extern __shared__ float4 er4[];                 // range phase factors of one pass
+    __shared__ ClusterShared sh;
+    float2* er = reinterpret_cast<float2*>(er4);
+    const int tid = threadIdx.x;
+    ClusterCtx cx;
+    const int lc = (int)blockIdx.x / cl.wgs;        // cell within the launch
+    cx.cell = cell0 + lc;
+    cx.part = (int)blockIdx.x - lc * cl.wgs;
+    cx.slot0 = lc * cl.wgs;
+    const int rows = g.k * g.mc;
+    cx.r0 = cx.part * cl.rows_per_wg;
+    cx.nrows = min(cl.rows_per_wg, rows - cx.r0);
+    cx.q_lo = cx.r0 >> g.log2_mc;
+    cx.nq = cl.rows_per_wg <= g.mc ? 1 : (cx.nrows + g.mc - 1) >> g.log2_mc;
+    double th0[4];
+    start_point(gp, cells[cx.cell], th0);
+    const double h[4] = {gp.step[0], gp.step[1], gp.step[2], gp.step[3]};
+    double z[4] = {0, 0, 0, 0};
+    unsigned pass = 0;
+    if (tid < 4) sh.th[0][tid] = th0[tid];
+    __syncthreads();
+    bool ok = cluster_pass(g, cl, cx, y, er, 1, pass, sh, ctr, abort_flag, part);
+    double d_cur = point_value(g, sh.mom[0]);
+    for (int e = tid; e < g.k * 12; e += kCT) sh.cur[e / 12][e % 12] = sh.mom[0][e / 12][e % 12];
+    __syncthreads();
+    for (int it = 0; ok && it < max_iter; ++it) {
+        double th[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) th[a] = th0[a] + z[a] * h[a];
+        if (tid < g.k) newton_terms(g, tid, th, sh.cur[tid], sh.terms[tid]);
+        __syncthreads();
+        if (tid < 14) {
+            double t = 0.0;
+            for (int q = 0; q < g.k; ++q) t += sh.terms[q][tid];
+            sh.tsum[tid] = t;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double t[14];
+#pragma unroll
+            for (int i = 0; i < 14; ++i) t[i] = sh.tsum[i];
+            newton_solve(t, h, sh.step);
+        }
+        __syncthreads();
+        double step[4], smax = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            step[a] = sh.step[a];
+            smax = fmax(smax, fabs(step[a]));
+        }
+        if (smax < kTol) break;
+        int acc_c = -1;
+        for (int tries = 0; tries < 16 && acc_c < 0;) {
+            const int npts = 16 - tries < kCand ? 16 - tries : kCand;
+#pragma unroll
+            for (int c = 0; c < kCand; ++c)
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const double v = fmin(1.0, fmax(-1.0, z[a] + step[a]));
+                    if (tid == 0 && c < npts) {
+                        sh.cand[c][a] = v;
+                        sh.th[c][a] = th0[a] + v * h[a];
+                    }
+                    step[a] *= (c < npts) ? 0.5 : 1.0;
+                }
+            __syncthreads();
+            if (!(ok = cluster_pass(g, cl, cx, y, er, npts, pass, sh, ctr, abort_flag, part))) break;
+            for (int c = 0; c < npts; ++c)
+                if (point_value(g, sh.mom[c]) >= d_cur) {
+                    acc_c = c;
+                    break;
+                }
+            tries += npts;
+        }
+        if (acc_c < 0) break;
+        const double d_new = point_value(g, sh.mom[acc_c]);
+        double move = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const double v = sh.cand[acc_c][a];
+            move = fmax(move, fabs(v - z[a]));
+            z[a] = v;
+        }
+        d_cur = d_new;
+        for (int e = tid; e < g.k * 12; e += kCT) sh.cur[e / 12][e % 12] = sh.mom[acc_c][e / 12][e % 12];
+        __syncthreads();
+        if (move < kTol) break;
+    }
+    if (cx.part == 0 && tid == 0)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) theta_out[(size_t)cx.cell * 4 + a] = ok ? th0[a] + z[a] * h[a] : NAN;
+}
+
+__global__ void refine_clear_kernel(unsigned* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+int pow2_at_least(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+Cluster cluster_plan(const Geom& g, int rows_per_wg, int ncells) {
+    Cluster cl;
+    const int rows = g.k * g.mc;
+    cl.rows_per_wg = rows_per_wg;
+    cl.wgs = (rows + rows_per_wg - 1) / rows_per_wg;
+    const long slots = (long)ncells * cl.wgs;
+    cl.slots = (int)(slots < kSlotsMax ? slots : kSlotsMax);
+    return cl;
+}
+
+// Largest rows per workgroup: one thread per (point, row), the range phase
+// table of the receivers it covers within kErMax, no more than the frame.
+int rows_max(const Geom& g) {
+    int r = kRowsMaxC;
+    while (r > g.mc && (long)kCand * (r / g.mc) * g.ms > kErMax) r >>= 1;
+    const int p2 = pow2_at_least(g.k * g.mc);
+    if (r > p2) r = p2;
+    return r < kRowsMinC ? kRowsMinC : r;
+}
+
+// Preferred rows per workgroup: about kWgsTarget workgroups per cell.
+// GH_REFINE_ROWS overrides it (tuning).
+int rows_pref(const Geom& g) {
+    int r = pow2_at_least((g.k * g.mc + kWgsTarget - 1) / kWgsTarget);
+    if (const char* e = getenv("GH_REFINE_ROWS")) {
+        const int v = atoi(e);
+        if (v > 0 && (v & (v - 1)) == 0) r = v;
+    }
+    const int hi = rows_max(g);
+    if (r > hi) r = hi;
+    return r < kRowsMinC ? kRowsMinC : r;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t counters_bytes(int ncells) { return align256(((size_t)ncells + 1) * sizeof(unsigned)); }
+
 }  // namespace
 
+size_t refine_ws_bytes(const Geom& g, int ncells) {
+    // the most slots any plan uses: the smallest rows per workgroup
+    const Cluster cl = cluster_plan(g, kRowsMinC, ncells);
+    return counters_bytes(ncells) + 2 * (size_t)cl.slots * kCand * kMaxRx * 12 * sizeof(double);
+}
+
 hipError_t launch_refine(const Geom& g, const GridP& gp, const float2* y, const int64_t* cells, int ncells,
-                         int max_iter, double* theta, hipStream_t st) {
-    hipLaunchKernelGGL(refine_kernel, dim3(ncells), dim3(kThreads), 0, st, g, gp, y, cells, max_iter, theta);
-    return hipGetLastError();
+                         int max_iter, void* ws, double* theta, hipStream_t st) {
+    // GH_REFINE_KERNEL = single selects the one-workgroup-per-cell kernel (diagnostics and tests)
+    const char* sel = getenv("GH_REFINE_KERNEL");
+    const bool single_only = sel && strcmp(sel, "single") == 0;
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int slots_cap = cluster_plan(g, kRowsMinC, ncells).slots;   // as sized by refine_ws_bytes
+    // preferred rows per workgroup, doubled while the cells need more than one launch
+    Cluster cl{};
+    long capacity = 0;
+    size_t lds = 0;
+    bool found = false;
+    for (int r = rows_pref(g); r <= rows_max(g); r <<= 1) {
+        Cluster c = cluster_plan(g, r, ncells);
+        const int nq = r <= g.mc ? 1 : r / g.mc;
+        const size_t l = (size_t)kCand * nq * g.ms * sizeof(float2);
+        int per_cu = 0;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                 &per_cu, reinterpret_cast<const void*>(refine_cluster_kernel), kCT, l)) != hipSuccess)
+            return e;
+        long cap = (long)cus * per_cu;
+        if (cap > slots_cap) cap = slots_cap;
+        if (cap < c.wgs) continue;
+        c.slots = slots_cap;
+        cl = c;
+        capacity = cap;
+        lds = l;
+        found = true;
+        if ((long)ncells * c.wgs <= cap) break;     // one launch holds every cell
+    }
+    if (single_only || !found) {
+        hipLaunchKernelGGL(refine_single_kernel, dim3(ncells), dim3(kThreads), 0, st, g, gp, y, cells, max_iter, theta);
+        return hipGetLastError();
+    }
+    unsigned* ctr = static_cast<unsigned*>(ws);
+    unsigned* abort_flag = ctr + ncells;
+    double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + counters_bytes(ncells));
+    hipLaunchKernelGGL(refine_clear_kernel, dim3((ncells + 256) / 256), dim3(256), 0, st, ctr, ncells + 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int batch = (int)(capacity / cl.wgs);
+    for (int c0 = 0; c0 < ncells; c0 += batch) {
+        const int nb = ncells - c0 < batch ? ncells - c0 : batch;
+        Geom ga = g;
+        GridP gpa = gp;
+        const float2* ya = y;
+        const int64_t* ca = cells;
+        int c0a = c0, mi = max_iter;
+        Cluster cla = cl;
+        double* ta = theta;
+        void* args[] = {&ga, &gpa, &ya, &ca, &c0a, &mi, &cla, &ta, &ctr, &abort_flag, &part};
+        e = hipLaunchKernel(reinterpret_cast<const void*>(refine_cluster_kernel), dim3(nb * cl.wgs), dim3(kCT), args,
+                            lds, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace gh

@@ -23,7 +23,8 @@ GEMM_F32, GEMM_BF16 = 0, 1
 MAX_SUPPORT = 32
 
 EXPORTS = ("gh_abi_version", "gh_last_error", "gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_workspace_bytes",
-           "gh_direct_decision", "gh_bomp_workspace_bytes", "gh_bomp_step", "gh_refine")
+           "gh_direct_decision", "gh_bomp_workspace_bytes", "gh_bomp_step", "gh_refine_workspace_bytes",
+           "gh_refine")
 
 
 class GhRadar(ctypes.Structure):
@@ -71,7 +72,9 @@ def load():
     lib.gh_bomp_workspace_bytes.argtypes = [rp, gp_, i32, i32]
     lib.gh_bomp_workspace_bytes.restype = sz
     lib.gh_bomp_step.argtypes = [rp, gp_, vp, vp, vp, i32, i32, i32, vp, i32, i32, vp, pp, vp, sz, vp]
-    lib.gh_refine.argtypes = [rp, gp_, vp, vp, i32, i32, vp, vp]
+    lib.gh_refine_workspace_bytes.argtypes = [rp, gp_, i32]
+    lib.gh_refine_workspace_bytes.restype = sz
+    lib.gh_refine.argtypes = [rp, gp_, vp, vp, i32, i32, vp, sz, vp, vp]
     for name in ("gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_decision", "gh_bomp_step", "gh_refine"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -246,13 +249,23 @@ class BompState:
         self.n += 1
 
 
-def refine(radar: Radar, grid: GhGrid, y, cells: torch.Tensor, max_iter=20, theta=None, stream=None):
+def refine_workspace_bytes(radar: Radar, grid: GhGrid, n_cells: int) -> int:
+    n = load().gh_refine_workspace_bytes(ctypes.byref(radar.c_struct), ctypes.byref(grid), int(n_cells))
+    if n == 0:
+        raise GridHopError(GH_EINVAL, last_error())
+    return n
+
+
+def refine(radar: Radar, grid: GhGrid, y, cells: torch.Tensor, max_iter=20, theta=None, ws=None, stream=None):
     lib = load()
     _c64(y)
     if cells.dtype != torch.int64 or not cells.is_cuda:
         raise ValueError("cells must be an int64 CUDA tensor")
     if theta is None:
         theta = torch.empty((cells.numel(), 4), dtype=torch.float64, device=y.device)
+    if ws is None and cells.numel() > 0:
+        ws = torch.empty(refine_workspace_bytes(radar, grid, cells.numel()), dtype=torch.uint8, device=y.device)
+    nws = 0 if ws is None else ws.numel()
     _check(lib.gh_refine(ctypes.byref(radar.c_struct), ctypes.byref(grid), _ptr(y), _ptr(cells), cells.numel(),
-                         int(max_iter), _ptr(theta), _stream(stream)))
+                         int(max_iter), _ptr(ws), nws, _ptr(theta), _stream(stream)))
     return theta

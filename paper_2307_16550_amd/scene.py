@@ -122,7 +122,10 @@ def full_grid(n) -> Grid:
     return Grid((X_LO[0], X_LO[1], V_LO[0], V_LO[1]), (X_HI[0], X_HI[1], V_HI[0], V_HI[1]), tuple(n))
 
 
-def draw_receivers(rng, k: int, half_span: float = 10.0, min_gap: float = 1.0) -> np.ndarray:
+def draw_receivers(rng, k: int, half_span: float = 10.0, min_gap: float | None = None) -> np.ndarray:
+    """k receivers uniform on the 20 m baseline x = 0, at least 1 m apart (closer for k > 8)."""
+    if min_gap is None:
+        min_gap = 1.0 if k <= 8 else half_span / (2 * k)
     while True:
         ys = rng.uniform(-half_span, half_span, size=k)
         if k < 2 or np.min(np.diff(np.sort(ys))) >= min_gap:

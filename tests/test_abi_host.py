@@ -109,15 +109,21 @@ def test_bomp_and_refine_argument_checks(lib):
     assert lib.gh_bomp_step(*args, 3, 3, FAKE, None, FAKE, ws, None) == gh.GH_EINVAL      # n_support == max
     assert lib.gh_bomp_step(*args, 0, 33, FAKE, None, FAKE, ws, None) == gh.GH_EINVAL     # max above limit
     assert lib.gh_bomp_step(*args, 0, 3, FAKE, None, FAKE, ws - 1, None) == gh.GH_EWORKSPACE
-    assert lib.gh_refine(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, FAKE, 1, 0, FAKE, None) == gh.GH_EINVAL
-    assert lib.gh_refine(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, FAKE, 0, 20, FAKE, None) == gh.GH_OK
+    rws = lib.gh_refine_workspace_bytes(ctypes.byref(r.c_struct), ctypes.byref(GRID), 3)
+    assert rws >= 2 * 3 * 3 * 12 * 8
+    assert lib.gh_refine_workspace_bytes(ctypes.byref(r.c_struct), ctypes.byref(GRID), 0) == 0
+    rargs = [ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, FAKE]
+    assert lib.gh_refine(*rargs, 1, 0, FAKE, rws, FAKE, None) == gh.GH_EINVAL           # max_iter 0
+    assert lib.gh_refine(*rargs, 3, 20, FAKE, rws - 1, FAKE, None) == gh.GH_EWORKSPACE
+    assert lib.gh_refine(*rargs, 3, 20, None, rws, FAKE, None) == gh.GH_EINVAL
+    assert lib.gh_refine(*rargs, 0, 20, None, 0, FAKE, None) == gh.GH_OK
 
 
 def test_error_message_cleared_after_success(lib):
     r = radar()
     lib.gh_rd_maps(None, FAKE, FAKE, None)
     assert gh.last_error()
-    assert lib.gh_refine(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, FAKE, 0, 20, FAKE, None) == gh.GH_OK
+    assert lib.gh_refine(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, FAKE, 0, 20, None, 0, FAKE, None) == gh.GH_OK
     assert gh.last_error() == ""
 
 
@@ -131,4 +137,5 @@ def test_misaligned_pointers_rejected(lib):
     need = lib.gh_direct_workspace_bytes(ctypes.byref(r.c_struct), ctypes.byref(GRID), 1)
     assert lib.gh_direct_decision(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, 1, odd, need, None, FAKE,
                                   None, None) == gh.GH_EINVAL
-    assert lib.gh_refine(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, odd, 1, 20, FAKE, None) == gh.GH_EINVAL
+    assert lib.gh_refine(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, odd, 1, 20, FAKE, 1 << 20, FAKE,
+                         None) == gh.GH_EINVAL

@@ -337,9 +337,12 @@ def test_bomp_fit_cfg2_full_size():
 
 # ---------------------------------------------------------------- refinement
 
+@pytest.mark.parametrize("kernel", ["cluster", "single"])
 @pytest.mark.parametrize("cfg,trial", [(1, 0), (1, 1), (2, 0)])
-def test_refine_parity(cfg, trial):
-    say(f"refine cfg={cfg} trial={trial}")
+def test_refine_parity(cfg, trial, kernel, monkeypatch):
+    say(f"refine cfg={cfg} trial={trial} kernel={kernel}")
+    if kernel == "single":
+        monkeypatch.setenv("GH_REFINE_KERNEL", "single")
     s, r, gr = scene_and_radar(cfg, trial)
     cells = [true_cell(s, t) for t in range(s.pos.shape[0])]
     th = gh.refine(gr, gh.grid_of(s.grid), to_dev(s.y), torch.tensor(cells, dtype=torch.int64, device=dev()))
@@ -355,3 +358,35 @@ def test_refine_noise_free_truth():
                    torch.tensor([true_cell(s)], dtype=torch.int64, device=dev()), max_iter=40)
     tg = th.cpu().numpy()[0]
     assert np.max(np.abs(tg[:2] - s.pos[0])) <= 1e-4 and np.max(np.abs(tg[2:] - s.vel[0])) <= 1e-4
+
+
+def test_refine_many_cells_in_batches():
+    """More cells than one cooperative launch holds: repeated starts give identical results."""
+    s, r, gr = scene_and_radar(2, 0)
+    cells = [true_cell(s, t) for t in range(s.pos.shape[0])]
+    rep = cells * 12
+    say(f"refine batches: {len(rep)} cells")
+    th = gh.refine(gr, gh.grid_of(s.grid), to_dev(s.y), torch.tensor(rep, dtype=torch.int64, device=dev()))
+    tg = th.cpu().numpy()
+    assert np.all(np.isfinite(tg))
+    for i in range(len(rep)):
+        assert np.array_equal(tg[i], tg[i % len(cells)])
+    tr = orefine.refine(s.y, r, s.grid, cells)
+    assert np.max(np.abs(tg[: len(cells)] - tr)) <= 1e-3
+
+
+@pytest.mark.parametrize("ms,mc,k,n", [(8, 8, 1, (4, 4, 3, 3)), (1024, 16, 2, (5, 5, 3, 3)), (16, 1024, 3, (3, 3, 5, 5)),
+                                       (64, 32, 16, (6, 6, 4, 4))])
+def test_refine_shapes(ms, mc, k, n):
+    """Cluster plans from one row per workgroup group to many receivers per workgroup."""
+    say(f"refine shapes ms={ms} mc={mc} k={k}")
+    s, r, gr = scene_and_radar(1, 4, ms=ms, mc=mc, k=k, snr_db=30.0)
+    grid = sc.Grid((4.0, -11.0, -11.0, -11.0), (26.0, 11.0, 11.0, 11.0), n)
+    ax = [grid.axis(a) for a in range(4)]
+    idx = [int(np.argmin(np.abs(ax[a] - (s.pos[0, a] if a < 2 else s.vel[0, a - 2])))) for a in range(4)]
+    cell = ((idx[0] * n[1] + idx[1]) * n[2] + idx[2]) * n[3] + idx[3]
+    th = gh.refine(gr, gh.grid_of(grid), to_dev(s.y), torch.tensor([cell], dtype=torch.int64, device=dev()))
+    tg = th.cpu().numpy()
+    tr = orefine.refine(s.y, r, grid, [cell])
+    assert np.max(np.abs(tg - tr)) <= 1e-3, (tg, tr)
+
