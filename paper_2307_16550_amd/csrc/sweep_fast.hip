@@ -14,9 +14,11 @@
 // (N_d > 512); the fraction b becomes the float 1 + b by inserting its top 23
 // bits into the mantissa of 1.0.
 //
-// Per receiver the workgroup first builds the Doppler tables of its locations
-// (coalesced: each thread a run of 4 entries, vector loads straight from the
-// maps, range rows and their wrap signs resolved once per location): the range
+// Per receiver each wave first builds its location's Doppler table in its own
+// LDS slice (coalesced: each lane builds runs of 2 (bilinear) or 4 (bicubic)
+// entries from vector loads straight from the maps, range rows and their wrap
+// signs resolved once per location; the next receiver's map values are
+// prefetched into registers while the current table is evaluated): the range
 // interpolation (2 or 4 map rows) collapses to a profile h[l], and each
 // segment [l, l+1] stores the Doppler interpolant as a polynomial in the
 // fraction:
