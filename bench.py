@@ -39,6 +39,28 @@ sys.path.insert(0, ROOT)
 CFG = 2
 HBM_PEAK_GBS = 8000.0
 BOMP_ITERS = 3
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "gh_sweep_columns_paper_scale_hbm_traffic.md")
+SWEEP_SOURCES = [os.path.join(ROOT, "paper_2307_16550_amd", "csrc", f) for f in ("sweep_fast.hip", "gh_internal.h")]
+
+
+def recorded_traffic():
+    """HBM bytes per sweep launch from the committed counter record, or None when
+    the sweep sources have changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_RECORD).read()
+        h = hashlib.sha256()
+        for f in SWEEP_SOURCES:
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    except OSError:
+        return None
+    m_bytes = re.search(r"^traffic_bytes_per_launch:\s*(\d+)", text, re.M)
+    m_sha = re.search(r"^sweep_source_sha256:\s*([0-9a-f]{64})", text, re.M)
+    if not m_bytes or not m_sha or m_sha.group(1) != h.hexdigest():
+        return None
+    return int(m_bytes.group(1))
 
 
 def parse():
@@ -286,7 +308,7 @@ def main():
         "speedup_gh_over_direct_per_point": (n_gh / (t_maps + t_sweep + t_arg)) / (n_dir / t_dir),
         "roofline": {"kernel": "gh_sweep_columns<bilinear>" if interp == gh.BILINEAR else "gh_sweep_columns<bicubic>",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(),
                      "algorithmic_bytes_per_launch": sweep_bytes,
                      "avg_launch_us": t_sweep * 1e6},
     }

@@ -1,67 +1,90 @@
 // Range-Doppler maps: per-receiver zero-padded 2D DFT (paper Sec. III and IV),
-//   Z_q[i][l] = sum_m sum_s Y_q[m][s] exp(-j 2 pi (i (s - c_s)/N_r + l (m - c_m)/N_d)).
+//   Z_q[i][l] = sum_m sum_s Y_q[m][s] exp(-j 2 pi (i (s - c_s)/N_r + l (m - c_m)/N_d)),
+// with c = (M - 1)/2 for centred maps and c = 0 otherwise.
 //
-// Two passes through the output buffer, each an LDS Stockham FFT:
-//   pass 1, range: one workgroup per (receiver, group of chirps).  Zero padding
-//     by P is pruned: output i = P*q + p is the length-Ms FFT (index q) of the
-//     chirp pre-twiddled by W_{N_r}^{p s}, so P short FFTs replace one long FFT
-//     over a 3/4-zero input.  The spectrum of chirp m is parked, transposed, in
-//     column m of the map rows (Z[q][i][m], m < Mc); a group of chirps per
-//     workgroup makes those stores contiguous runs.
-//   pass 2, Doppler: one workgroup per (receiver, group of range bins) reads the
-//     first Mc entries of its rows, transforms them the same way along slow
-//     time and overwrites the whole rows (each row is read and written by one
-//     workgroup only, so the pass is in place).
-// Centring multiplies output bin i by exp(j pi i (M-1)/N) (shift theorem).
+// Zero padding by P is pruned on both axes: output bin P k + p of a length-N
+// transform (N = P M) of a length-M sequence x is
+//   e^{j 2 pi (P k + p) c / N} sum_s x[s] W_N^{p s} W_M^{k s}
+//   = cen[k] * FFT_M( x[s] * pre_p[s] )[k],
+//   pre_p[s] = exp(-j pi p (2 s - 2 c) / N),   cen[k] = exp(j 2 pi k c / M),
+// so P short FFTs on pre-twiddled inputs replace one long FFT over a mostly
+// zero input, and the centring costs one table product per element.  Tables
+// are built per workgroup with exact integer argument reduction.
+//
+// Two passes through the output buffer, each an LDS Stockham FFT (radix 4/2):
+//   pass 1, range: one workgroup per (receiver, sub-transform p, group of G
+//     chirps); the spectra are parked, transposed, in columns m < Mc of the map
+//     rows (Z[q][P k + p][m]), G consecutive chirps per store run.
+//   pass 2, Doppler: one workgroup per (receiver, group of range rows) reads the
+//     first Mc entries of its rows, applies the P sub-transforms and overwrites
+//     the whole rows (each row is read and written by one workgroup only).
+// LDS sequences are padded to an odd stride so the transposed reads of the
+// store phase do not conflict.
 #include "gh_internal.h"
 
 namespace gh {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kLdsElems = 4096;   // complex values of the work buffer per workgroup (32 KiB)
+constexpr int kBuf = 4096;        // complex values of FFT work per workgroup
 
-// Twiddle table W_N^t = exp(-j 2 pi t / N), t < N, exact argument reduction.
-__device__ void fill_twiddles(float2* tw, int n, int log2n) {
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        float s, c;
-        // angle = -2 pi t / n = -pi * (2t/n); 2t/n is exact in float for n <= 2^24
-        sincospif(__int2float_rn(2 * t) / __int2float_rn(n), &s, &c);
-        tw[t] = make_float2(c, -s);
+// exp(-j pi num / den) with the numerator reduced exactly modulo 2 den.
+__device__ __forceinline__ float2 expm_pi(long long num, int den) {
+    const long long two = 2LL * den;
+    long long r = num % two;
+    if (r < 0) r += two;
+    float s, c;
+    sincospif((float)r / (float)den, &s, &c);
+    return make_float2(c, -s);
+}
+
+// pre[s] = exp(-j pi p (2 s - c2) / N) for s < M (c2 = M - 1 when centred, else 0;
+// for every p < np when all_p, none when np == 0), tw[t] = W_M^t for t < M,
+// cen[k] = exp(+j pi k c2 / M) for k < M.
+__device__ void fill_tables(float2* pre, float2* tw, float2* cen, int p, int m, int n, int centered,
+                            bool all_p, int np) {
+    const int c2 = centered ? m - 1 : 0;
+    const int npre = all_p ? np * m : (np > 0 ? m : 0);
+    for (int t = threadIdx.x; t < npre; t += blockDim.x) {
+        const int pp = all_p ? t / m : p;
+        const int s = all_p ? t - pp * m : t;
+        pre[t] = expm_pi((long long)pp * (2LL * s - c2), n);
+    }
+    for (int t = threadIdx.x; t < m; t += blockDim.x) {
+        tw[t] = expm_pi(2LL * t, m);
+        const float2 e = expm_pi((long long)t * c2, m);
+        cen[t] = make_float2(e.x, -e.y);
     }
 }
 
-// In-place forward FFTs of `nseq` contiguous sequences of length m = 2^log2m
-// held in LDS buf[nseq][m].  Mixed radix-4/2 Stockham iterations; each stage
-// reads all operands to registers, synchronises, then writes.  `tw` is the
-// table of W_N^t with N = m * tw_stride.
-__device__ void lds_fft(float2* buf, int nseq, int log2m, const float2* tw, int tw_stride) {
+// In-place forward FFTs of `nseq` sequences of length m = 2^log2m, sequence j at
+// buf + j * stride.  Mixed radix-4/2 Stockham iterations; each stage reads all
+// operands to registers, synchronises, then writes.  tw[t] = W_m^t.
+__device__ void lds_fft(float2* buf, int nseq, int stride, int log2m, const float2* tw) {
     const int m = 1 << log2m;
-    const int total = nseq * m;
-    int ns = 1;
+    int ns = 1, log2ns = 0;
     int remaining = log2m;
     while (remaining > 0) {
-        const int radix = (remaining >= 2) ? 4 : 2;
-        const int log2r = (radix == 4) ? 2 : 1;
-        const int nbf = total >> log2r;          // butterflies in this stage
-        const int per_seq = m >> log2r;
-        // at most kLdsElems / 2 / kThreads = 8 butterflies per thread (static
-        // register indexing: the loop bound is a compile-time constant)
+        const int log2r = (remaining >= 2) ? 2 : 1;
+        const int per_seq = m >> log2r;               // butterflies per sequence
+        const int log2ps = log2m - log2r;
+        const int nbf = nseq << log2ps;
+        // at most kBuf / 2 / kThreads = 8 butterflies per thread (static register indexing)
         float2 v[8][4];
         int dst[8];
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const int b = threadIdx.x + c * kThreads;
             if (b < nbf) {
-                const int seq = b / per_seq;
-                const int j = b - seq * per_seq;
+                const int seq = b >> log2ps;
+                const int j = b & (per_seq - 1);
                 const int jm = j & (ns - 1);
-                const float2* base = buf + seq * m;
-                // twiddle exponent jm * r * m / (ns * radix), as an index into W_N
-                const int tstep = (jm * (m / (ns * radix))) * tw_stride;
+                const float2* base = buf + seq * stride;
+                // twiddle exponent jm * m / (ns * radix)
+                const int tstep = jm << (log2m - log2ns - log2r);
                 const float2 a0 = base[j];
                 const float2 a1 = cmul(base[j + per_seq], tw[tstep]);
-                if (radix == 4) {
+                if (log2r == 2) {
                     const float2 a2 = cmul(base[j + 2 * per_seq], tw[2 * tstep]);
                     const float2 a3 = cmul(base[j + 3 * per_seq], tw[3 * tstep]);
                     const float2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
@@ -77,7 +100,7 @@ __device__ void lds_fft(float2* buf, int nseq, int log2m, const float2* tw, int 
                     v[c][2] = v[c][1];
                     v[c][3] = v[c][1];
                 }
-                dst[c] = seq * m + (j - jm) * radix + jm;
+                dst[c] = seq * stride + ((j - jm) << log2r) + jm;
             }
         }
         __syncthreads();
@@ -87,98 +110,123 @@ __device__ void lds_fft(float2* buf, int nseq, int log2m, const float2* tw, int 
             if (b < nbf) {
                 buf[dst[c]] = v[c][0];
                 buf[dst[c] + ns] = v[c][1];
-                if (radix == 4) {
+                if (log2r == 2) {
                     buf[dst[c] + 2 * ns] = v[c][2];
                     buf[dst[c] + 3 * ns] = v[c][3];
                 }
             }
         }
         __syncthreads();
-        ns *= radix;
+        ns <<= log2r;
+        log2ns += log2r;
         remaining -= log2r;
     }
 }
 
-// exp(+j pi i (M-1) / N), exact reduction of i (M-1) modulo 2N.
-__device__ __forceinline__ float2 centring_phase(int i, int mlen, int n) {
-    const long long num = ((long long)i * (mlen - 1)) % (2LL * n);
-    float s, c;
-    sincospif((float)num / __int2float_rn(n), &s, &c);
-    return make_float2(c, s);
-}
-
-// Pass 1: range FFT of `nch` chirps per workgroup.
+// Pass 1: range sub-transform p of `nch` chirps of receiver q.
 __global__ __launch_bounds__(kThreads) void range_pass(Geom g, int nch, const float2* __restrict__ y,
                                                       float2* __restrict__ maps) {
-    __shared__ float2 buf[kLdsElems];
-    __shared__ float2 tw[4096];
-    const int q = blockIdx.y;
+    extern __shared__ float2 lds[];
+    const int ms = g.ms, stride = ms + 1;
+    float2* buf = lds;                        // [nch][ms + 1]
+    float2* pre = buf + nch * stride;         // [ms]
+    float2* tw = pre + ms;                    // [ms]
+    float2* cen = tw + ms;                    // [ms]
     const int m0 = blockIdx.x * nch;
-    const int ms = g.ms, nr = g.nr, pr = g.pr;
-    fill_twiddles(tw, nr, g.log2_nr);
+    const int p = blockIdx.y;
+    const int q = blockIdx.z;
+    // the inputs are loaded first so that the table build hides their latency
+    const float2* yq = y + ((size_t)q * g.mc + m0) * ms;
+    float2 x[kBuf / kThreads];
+#pragma unroll
+    for (int j = 0; j < kBuf / kThreads; ++j) {
+        const int e = threadIdx.x + j * kThreads;
+        if (e < nch * ms) x[j] = yq[e];
+    }
+    fill_tables(pre, tw, cen, p, ms, g.nr, g.centered, false, 1);
     __syncthreads();
-    // pre-twiddled, pruned input: buf[c][p][s] = y[m0+c][s] * W_Nr^{p s}
-    const int total = nch * nr;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const int s = e & (ms - 1);
-        const int p = (e >> g.log2_ms) % pr;
-        const int c = e / nr;
-        const float2 v = y[((size_t)q * g.mc + m0 + c) * ms + s];
-        buf[e] = cmul(v, tw[p * s]);
+#pragma unroll
+    for (int j = 0; j < kBuf / kThreads; ++j) {
+        const int e = threadIdx.x + j * kThreads;
+        if (e < nch * ms) {
+            const int c = e >> g.log2_ms, s = e & (ms - 1);
+            buf[c * stride + s] = cmul(x[j], pre[s]);
+        }
     }
     __syncthreads();
-    lds_fft(buf, nch * pr, g.log2_ms, tw, pr);
-    // out bin i = pr*qq + p lives at buf[c][p][qq]; store transposed: Z[q][i][m0 + c]
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const int c = e % nch;
-        const int i = e / nch;
-        const int p = i % pr, qq = i / pr;
-        float2 v = buf[c * nr + p * ms + qq];
-        if (g.centered) v = cmul(v, centring_phase(i, ms, nr));
-        maps[((size_t)q * nr + i) * g.nd + m0 + c] = v;
+    lds_fft(buf, nch, stride, g.log2_ms, tw);
+    // out bin i = P k + p of chirp m0 + c: Z[q][i][m0 + c], chirps fastest
+    const int log2n = 31 - __clz(nch);
+    for (int e = threadIdx.x; e < nch * ms; e += kThreads) {
+        const int c = e & (nch - 1), k = e >> log2n;
+        const float2 v = cmul(buf[c * stride + k], cen[k]);
+        maps[((size_t)q * g.nr + (size_t)k * g.pr + p) * g.nd + m0 + c] = v;
     }
 }
 
-// Pass 2: Doppler FFT of `nrow` range bins per workgroup, in place.
-__global__ __launch_bounds__(kThreads) void doppler_pass(Geom g, int nrow, float2* __restrict__ maps) {
-    __shared__ float2 buf[kLdsElems];
-    __shared__ float2 tw[4096];
+// Pass 2: Doppler transforms of `nrow` range rows of receiver q, in place.
+// With `pre_lds` false (the largest maps) the pre-twiddles are evaluated inline
+// instead of from an LDS table.
+__global__ __launch_bounds__(kThreads) void doppler_pass(Geom g, int nrow, int pre_lds, float2* __restrict__ maps) {
+    extern __shared__ float2 lds[];
+    const int mc = g.mc, pd = g.pd, nd = g.nd, stride = mc + 1;
+    const int log2pd = __ffs(pd) - 1;
+    float2* buf = lds;                        // [nrow][pd][mc + 1]
+    float2* tw = buf + nrow * pd * stride;    // [mc]
+    float2* cen = tw + mc;                    // [mc]
+    float2* pre = cen + mc;                   // [pd][mc] (pre_lds)
     const int q = blockIdx.y;
     const int i0 = blockIdx.x * nrow;
-    const int mc = g.mc, nd = g.nd, pd = g.pd;
-    fill_twiddles(tw, nd, g.log2_nd);
+    float2* rows = maps + ((size_t)q * g.nr + i0) * nd;
+    // the inputs (nrow * mc <= kBuf) are loaded first so that the table build hides their latency
+    float2 x[kBuf / kThreads];
+#pragma unroll
+    for (int j = 0; j < kBuf / kThreads; ++j) {
+        const int e = threadIdx.x + j * kThreads;
+        if (e < nrow * mc) x[j] = rows[(size_t)(e >> g.log2_mc) * nd + (e & (mc - 1))];
+    }
+    fill_tables(pre, tw, cen, 0, mc, nd, g.centered, pre_lds != 0, pre_lds ? pd : 0);
     __syncthreads();
-    const int total = nrow * nd;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const int m = e & (mc - 1);
-        const int p = (e >> g.log2_mc) % pd;
-        const int r = e / nd;
-        const float2 v = maps[((size_t)q * g.nr + i0 + r) * nd + m];
-        buf[e] = cmul(v, tw[p * m]);
+    const int c2 = g.centered ? mc - 1 : 0;
+#pragma unroll
+    for (int j = 0; j < kBuf / kThreads; ++j) {
+        const int e = threadIdx.x + j * kThreads;
+        if (e < nrow * mc) {
+            const int r = e >> g.log2_mc, m = e & (mc - 1);
+            for (int p = 0; p < pd; ++p) {
+                const float2 w = pre_lds ? pre[p * mc + m] : expm_pi((long long)p * (2LL * m - c2), nd);
+                buf[(r * pd + p) * stride + m] = cmul(x[j], w);
+            }
+        }
     }
     __syncthreads();
-    lds_fft(buf, nrow * pd, g.log2_mc, tw, pd);
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const int l = e & (nd - 1);
-        const int r = e >> g.log2_nd;
-        const int p = l % pd, qq = l / pd;
-        float2 v = buf[r * nd + p * mc + qq];
-        if (g.centered) v = cmul(v, centring_phase(l, mc, nd));
-        maps[((size_t)q * g.nr + i0 + r) * nd + l] = v;
+    lds_fft(buf, nrow * pd, stride, g.log2_mc, tw);
+    // out bin l = P k + p, bins fastest
+    for (int e = threadIdx.x; e < nrow * nd; e += kThreads) {
+        const int r = e >> g.log2_nd, l = e & (nd - 1);
+        const int k = l >> log2pd, p = l & (pd - 1);
+        rows[(size_t)r * nd + l] = cmul(buf[(r * pd + p) * stride + k], cen[k]);
     }
 }
 
 }  // namespace
 
 hipError_t launch_rd_maps(const Geom& g, const float2* y, float2* maps, hipStream_t st) {
-    int nch = kLdsElems / g.nr;
+    // range pass: chirps per workgroup, halved (down to 8) until there are >= 512 workgroups
+    int nch = kBuf / g.ms;
     if (nch > g.mc) nch = g.mc;
-    int nrow = kLdsElems / g.nd;
-    if (nrow > g.nr) nrow = g.nr;
-    hipLaunchKernelGGL(range_pass, dim3(g.mc / nch, g.k), dim3(kThreads), 0, st, g, nch, y, maps);
+    while (nch > 8 && (long)(g.mc / nch) * g.pr * g.k < 512) nch >>= 1;
+    const size_t lds1 = ((size_t)nch * (g.ms + 1) + 3 * (size_t)g.ms) * sizeof(float2);
+    hipLaunchKernelGGL(range_pass, dim3(g.mc / nch, g.pr, g.k), dim3(kThreads), lds1, st, g, nch, y, maps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(doppler_pass, dim3(g.nr / nrow, g.k), dim3(kThreads), 0, st, g, nrow, maps);
+    int nrow = kBuf / g.nd;
+    if (nrow < 1) nrow = 1;
+    if (nrow > g.nr) nrow = g.nr;
+    size_t lds2 = ((size_t)nrow * g.pd * (g.mc + 1) + 2 * (size_t)g.mc) * sizeof(float2);
+    const int pre_lds = lds2 + (size_t)g.nd * sizeof(float2) <= 65536 ? 1 : 0;
+    if (pre_lds) lds2 += (size_t)g.nd * sizeof(float2);
+    hipLaunchKernelGGL(doppler_pass, dim3(g.nr / nrow, g.k), dim3(kThreads), lds2, st, g, nrow, pre_lds, maps);
     return hipGetLastError();
 }
 
