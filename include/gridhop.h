@@ -62,6 +62,13 @@ typedef enum {
 
 typedef enum { GH_INTERP_BILINEAR = 0, GH_INTERP_BICUBIC = 1 } gh_interp;
 
+/* Storage of range-Doppler maps.  GH_MAP_C64: complex64, the map itself.
+ * GH_MAP_F16 / GH_MAP_BF16: (re, im) pairs of IEEE binary16 / bfloat16
+ * holding Z / (Ms * Mc), an exact power of two that keeps FP16 in range
+ * (|Z| <= Ms * Mc * sum |y|); decisions computed from them are rescaled
+ * exactly.  The half formats need pad_doppler >= 2. */
+typedef enum { GH_MAP_C64 = 0, GH_MAP_F16 = 1, GH_MAP_BF16 = 2 } gh_map_dtype;
+
 typedef enum { GH_GEMM_F32 = 0, GH_GEMM_BF16 = 1 } gh_gemm_dtype;
 
 /* Radar and frame description (paper Sec. II).  Limits: n_samples and
@@ -113,22 +120,23 @@ const char *gh_last_error(void);
  *               exp(-j 2 pi (i (s - c_s) / N_r + l (m - c_m) / N_d)),
  * c_s = (Ms-1)/2, c_m = (Mc-1)/2 if radar->centered, else 0: the zero-padded
  * (zeros appended, rectangular window) forward 2D DFT.
- * d_y: complex64 [K][Mc][Ms] (read only).  d_maps: complex64 [K][N_r][N_d]
- * (written; must not overlap d_y).  FP32 arithmetic. */
-int gh_rd_maps(const gh_radar *radar, const void *d_y, void *d_maps, void *stream);
+ * d_y: complex64 [K][Mc][Ms] (read only).  d_maps: [K][N_r][N_d] in the
+ * storage `map_dtype` (gh_map_dtype; written; must not overlap d_y).  FP32
+ * arithmetic, rounded once to the storage type. */
+int gh_rd_maps(const gh_radar *radar, const void *d_y, void *d_maps, int32_t map_dtype, void *stream);
 
 /* Grid-hopping decision (paper Sec. IV, eq. (7)): for every grid point and
  * receiver q, interpolate map q at (t_r, t_d) (bilinear: 2x2 taps; bicubic:
  * 4x4 Keys taps, a = -1/2; periodic in both map axes, with the sign
  * (-1)^(M-1) per period for centred maps) and sum |.|^2 over receivers:
  *   D_gh(x, v) = sum_q |I(Z_q; t_r, t_d)|^2.
- * d_maps: output of gh_rd_maps for the same radar.
+ * d_maps: output of gh_rd_maps for the same radar, in storage `map_dtype`.
  * d_decision: float volume (NULL: not written, argmax only).
  * d_block: gh_peak [Nx*Ny], per-location maxima (required).
  * d_argmax: gh_peak [1], global maximum (NULL: not computed).
  * FP32 interpolation and accumulation; geometry in FP64, Doppler coordinate
  * in 32-bit fixed point (exact wrap). */
-int gh_decision(const gh_radar *radar, const gh_grid *grid, const void *d_maps, int32_t interp,
+int gh_decision(const gh_radar *radar, const gh_grid *grid, const void *d_maps, int32_t map_dtype, int32_t interp,
                 float *d_decision, gh_peak *d_block, gh_peak *d_argmax, void *stream);
 
 /* Global maximum of per-location peaks (the argmax of eqs. (5)-(6) over the

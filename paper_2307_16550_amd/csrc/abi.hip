@@ -129,6 +129,15 @@ int check_gemm(int gemm) {
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// The half storage formats park complex64 range spectra in their rows, which
+// needs N_d * 4 >= Mc * 8 bytes.
+int check_map_dtype(const gh::Geom& g, int dt) {
+    if (dt != GH_MAP_C64 && dt != GH_MAP_F16 && dt != GH_MAP_BF16)
+        return fail(GH_EINVAL, "map_dtype must be GH_MAP_C64, GH_MAP_F16 or GH_MAP_BF16");
+    if (dt != GH_MAP_C64 && g.pd < 2) return fail(GH_EUNSUPPORTED, "16-bit map storage needs pad_doppler >= 2");
+    return GH_OK;
+}
+
 // Device arrays are read and written with 16-byte vector accesses.
 int check_aligned(std::initializer_list<const void*> ptrs) {
     for (const void* p : ptrs)
@@ -144,32 +153,34 @@ int gh_abi_version(void) { return GH_ABI_VERSION; }
 
 const char* gh_last_error(void) { return g_err; }
 
-int gh_rd_maps(const gh_radar* radar, const void* d_y, void* d_maps, void* stream) {
+int gh_rd_maps(const gh_radar* radar, const void* d_y, void* d_maps, int32_t map_dtype, void* stream) {
     gh::Geom g;
     int rc = make_geom(radar, g);
-    if (rc) return rc;
+    if (rc || (rc = check_map_dtype(g, map_dtype))) return rc;
     if (!d_y || !d_maps) return fail(GH_EINVAL, "d_y and d_maps must be non-NULL");
     if ((rc = check_aligned({d_y, d_maps}))) return rc;
-    const size_t ybytes = (size_t)g.k * g.mc * g.ms * 8, mbytes = (size_t)g.k * g.nr * g.nd * 8;
+    const size_t ybytes = (size_t)g.k * g.mc * g.ms * 8,
+                 mbytes = (size_t)g.k * g.nr * g.nd * gh::map_elem_bytes(map_dtype);
     const char *y0 = (const char*)d_y, *m0 = (const char*)d_maps;
     if (y0 < m0 + mbytes && m0 < y0 + ybytes) return fail(GH_EINVAL, "d_y and d_maps overlap");
     if ((rc = check_device())) return rc;
-    hipError_t e = gh::launch_rd_maps(g, (const float2*)d_y, (float2*)d_maps, (hipStream_t)stream);
+    hipError_t e = gh::launch_rd_maps(g, (const float2*)d_y, d_maps, map_dtype, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gh_rd_maps launch");
     return ok();
 }
 
-int gh_decision(const gh_radar* radar, const gh_grid* grid, const void* d_maps, int32_t interp, float* d_decision,
-                gh_peak* d_block, gh_peak* d_argmax, void* stream) {
+int gh_decision(const gh_radar* radar, const gh_grid* grid, const void* d_maps, int32_t map_dtype, int32_t interp,
+                float* d_decision, gh_peak* d_block, gh_peak* d_argmax, void* stream) {
     gh::Geom g;
     gh::GridP gp;
     int rc = make_geom(radar, g);
-    if (rc || (rc = make_grid(grid, gp)) || (rc = check_sweep_limits(g, interp))) return rc;
+    if (rc || (rc = make_grid(grid, gp)) || (rc = check_sweep_limits(g, interp)) || (rc = check_map_dtype(g, map_dtype)))
+        return rc;
     if (!d_maps || !d_block) return fail(GH_EINVAL, "d_maps and d_block must be non-NULL");
     if ((rc = check_aligned({d_maps, d_decision, d_block, d_argmax}))) return rc;
     if ((rc = check_device())) return rc;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = gh::launch_gh_sweep(g, gp, (const float2*)d_maps, interp, d_decision, d_block, nullptr, 0, st);
+    hipError_t e = gh::launch_gh_sweep(g, gp, d_maps, map_dtype, interp, d_decision, d_block, nullptr, 0, st);
     if (e == hipSuccess && d_argmax) e = gh::launch_peak_final(d_block, gp.nloc, d_argmax, nullptr, st);
     if (e != hipSuccess) return hip_fail(e, "gh_decision launch");
     return ok();
@@ -252,9 +263,9 @@ int gh_bomp_step(const gh_radar* radar, const gh_grid* grid, const void* d_y, vo
     if (use_direct) {
         e = gh::launch_direct(g, gp, (const float2*)d_resid, gemm_dtype, dir_ws, nullptr, block, d_support, n_support, st);
     } else {
-        e = gh::launch_rd_maps(g, (const float2*)d_resid, (float2*)d_maps, st);
+        e = gh::launch_rd_maps(g, (const float2*)d_resid, d_maps, GH_MAP_C64, st);
         if (e == hipSuccess)
-            e = gh::launch_gh_sweep(g, gp, (const float2*)d_maps, interp, nullptr, block, d_support, n_support, st);
+            e = gh::launch_gh_sweep(g, gp, d_maps, GH_MAP_C64, interp, nullptr, block, d_support, n_support, st);
     }
     if (e == hipSuccess) e = gh::launch_peak_final(block, gp.nloc, d_selected, d_support + n_support, st);
     if (e == hipSuccess)

@@ -69,6 +69,48 @@ __host__ __device__ __forceinline__ uint32_t cycles_to_fixed_step(double cyc) {
     return cycles_to_fixed(cyc);  // modular arithmetic: the step is also taken mod 1 cycle
 }
 
+// ---- map storage (gh_map_dtype) ---------------------------------------------
+// Bytes per complex map value: 8 (complex64) or 4 (a pair of 16-bit floats).
+__host__ __device__ constexpr int map_elem_bytes(int dt) { return dt == GH_MAP_C64 ? 8 : 4; }
+
+__device__ __forceinline__ float half_bits_to_float(uint32_t bits, int dt) {
+    if (dt == GH_MAP_BF16) return __uint_as_float(bits << 16);
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)bits);
+}
+
+__device__ __forceinline__ uint32_t float_to_half_bits(float v, int dt) {
+    if (dt == GH_MAP_BF16) return (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)v);
+    return (uint32_t)__builtin_bit_cast(unsigned short, (_Float16)v);
+}
+
+// One complex map value at byte offset `off`.
+template <int DT>
+__device__ __forceinline__ float2 map_ld1(const char* base, uint32_t off) {
+    if constexpr (DT == GH_MAP_C64) {
+        return *reinterpret_cast<const float2*>(base + off);
+    } else {
+        const uint32_t u = *reinterpret_cast<const uint32_t*>(base + off);
+        return make_float2(half_bits_to_float(u & 0xffffu, DT), half_bits_to_float(u >> 16, DT));
+    }
+}
+
+// Two consecutive complex map values at byte offset `off` as (re0, im0, re1, im1).
+template <int DT>
+__device__ __forceinline__ float4 map_ld2(const char* base, uint32_t off) {
+    if constexpr (DT == GH_MAP_C64) {
+        return *reinterpret_cast<const float4*>(base + off);
+    } else {
+        const uint2 u = *reinterpret_cast<const uint2*>(base + off);
+        return make_float4(half_bits_to_float(u.x & 0xffffu, DT), half_bits_to_float(u.x >> 16, DT),
+                           half_bits_to_float(u.y & 0xffffu, DT), half_bits_to_float(u.y >> 16, DT));
+    }
+}
+
+// Scale of the stored maps: the half formats hold Z / (Ms * Mc).
+__host__ __device__ __forceinline__ float map_scale(int ms, int mc, int dt) {
+    return dt == GH_MAP_C64 ? 1.f : (float)ms * (float)mc;
+}
+
 // Bistatic geometry of one location and receiver, FP64.
 __device__ __forceinline__ void bistatic(const Geom& g, int q, double x, double y, double& r, double& wx,
                                          double& wy) {
@@ -147,17 +189,17 @@ __device__ __forceinline__ int local_exclusions(const int64_t* excl, int nexcl, 
 
 // ---- host launchers (return hipError_t of the launches) --------------------
 
-hipError_t launch_rd_maps(const Geom& g, const float2* y, float2* maps, hipStream_t st);
+hipError_t launch_rd_maps(const Geom& g, const float2* y, void* maps, int map_dtype, hipStream_t st);
 
-hipError_t launch_gh_sweep(const Geom& g, const GridP& gp, const float2* maps, int interp, float* dec,
+hipError_t launch_gh_sweep(const Geom& g, const GridP& gp, const void* maps, int map_dtype, int interp, float* dec,
                            gh_peak* block, const int64_t* excl, int nexcl, hipStream_t st);
 
 // Column variant of the sweep (power-of-two vy slabs); plan() returns false
 // when the shape needs the generic kernel.
 bool sweep_columns_plan(const Geom& g, const GridP& gp, int interp, int& lpb, int& log2nvy, size_t& lds);
 hipError_t launch_gh_sweep_columns(const Geom& g, const GridP& gp, int lpb, int log2nvy, size_t lds,
-                                   const float2* maps, int interp, float* dec, gh_peak* block, const int64_t* excl,
-                                   int nexcl, hipStream_t st);
+                                   const void* maps, int map_dtype, int interp, float* dec, gh_peak* block,
+                                   const int64_t* excl, int nexcl, hipStream_t st);
 
 hipError_t launch_peak_final(const gh_peak* block, int nblock, gh_peak* out, int64_t* support_slot,
                              hipStream_t st);

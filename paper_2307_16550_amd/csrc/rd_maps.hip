@@ -17,7 +17,10 @@
 //     rows (Z[q][P k + p][m]), G consecutive chirps per store run.
 //   pass 2, Doppler: one workgroup per (receiver, group of range rows) reads the
 //     first Mc entries of its rows, applies the P sub-transforms and overwrites
-//     the whole rows (each row is read and written by one workgroup only).
+//     the whole rows (each row is read and written by one workgroup only) in
+//     the storage type: complex64, or 16-bit pairs holding Z / (Ms Mc) (a half
+//     row of N_d 4-byte entries still holds the Mc 8-byte parked values when
+//     P_d >= 2).
 // LDS sequences are padded to an odd stride so the transposed reads of the
 // store phase do not conflict.
 #include "gh_internal.h"
@@ -123,9 +126,11 @@ __device__ void lds_fft(float2* buf, int nseq, int stride, int log2m, const floa
     }
 }
 
-// Pass 1: range sub-transform p of `nch` chirps of receiver q.
-__global__ __launch_bounds__(kThreads) void range_pass(Geom g, int nch, const float2* __restrict__ y,
-                                                      float2* __restrict__ maps) {
+// Pass 1: range sub-transform p of `nch` chirps of receiver q.  Map rows are
+// `row_bytes` apart (N_d times the storage size); the spectra are parked as
+// complex64 in the first Mc * 8 bytes of each row.
+__global__ __launch_bounds__(kThreads) void range_pass(Geom g, int nch, size_t row_bytes, const float2* __restrict__ y,
+                                                      char* __restrict__ maps) {
     extern __shared__ float2 lds[];
     const int ms = g.ms, stride = ms + 1;
     float2* buf = lds;                        // [nch][ms + 1]
@@ -160,14 +165,17 @@ __global__ __launch_bounds__(kThreads) void range_pass(Geom g, int nch, const fl
     for (int e = threadIdx.x; e < nch * ms; e += kThreads) {
         const int c = e & (nch - 1), k = e >> log2n;
         const float2 v = cmul(buf[c * stride + k], cen[k]);
-        maps[((size_t)q * g.nr + (size_t)k * g.pr + p) * g.nd + m0 + c] = v;
+        float2* row = reinterpret_cast<float2*>(maps + ((size_t)q * g.nr + (size_t)k * g.pr + p) * row_bytes);
+        row[m0 + c] = v;
     }
 }
 
-// Pass 2: Doppler transforms of `nrow` range rows of receiver q, in place.
+// Pass 2: Doppler transforms of `nrow` range rows of receiver q, in place, and
+// the conversion to the storage type DT (half formats: times 1 / (Ms Mc)).
 // With `pre_lds` false (the largest maps) the pre-twiddles are evaluated inline
 // instead of from an LDS table.
-__global__ __launch_bounds__(kThreads) void doppler_pass(Geom g, int nrow, int pre_lds, float2* __restrict__ maps) {
+template <int DT>
+__global__ __launch_bounds__(kThreads) void doppler_pass(Geom g, int nrow, int pre_lds, char* __restrict__ maps) {
     extern __shared__ float2 lds[];
     const int mc = g.mc, pd = g.pd, nd = g.nd, stride = mc + 1;
     const int log2pd = __ffs(pd) - 1;
@@ -177,13 +185,15 @@ __global__ __launch_bounds__(kThreads) void doppler_pass(Geom g, int nrow, int p
     float2* pre = cen + mc;                   // [pd][mc] (pre_lds)
     const int q = blockIdx.y;
     const int i0 = blockIdx.x * nrow;
-    float2* rows = maps + ((size_t)q * g.nr + i0) * nd;
+    constexpr int kEs = map_elem_bytes(DT);
+    const size_t row_bytes = (size_t)nd * kEs;
+    char* rowb = maps + ((size_t)q * g.nr + i0) * row_bytes;
     // the inputs (nrow * mc <= kBuf) are loaded first so that the table build hides their latency
     float2 x[kBuf / kThreads];
 #pragma unroll
     for (int j = 0; j < kBuf / kThreads; ++j) {
         const int e = threadIdx.x + j * kThreads;
-        if (e < nrow * mc) x[j] = rows[(size_t)(e >> g.log2_mc) * nd + (e & (mc - 1))];
+        if (e < nrow * mc) x[j] = reinterpret_cast<const float2*>(rowb + (size_t)(e >> g.log2_mc) * row_bytes)[e & (mc - 1)];
     }
     fill_tables(pre, tw, cen, 0, mc, nd, g.centered, pre_lds != 0, pre_lds ? pd : 0);
     __syncthreads();
@@ -202,22 +212,32 @@ __global__ __launch_bounds__(kThreads) void doppler_pass(Geom g, int nrow, int p
     __syncthreads();
     lds_fft(buf, nrow * pd, stride, g.log2_mc, tw);
     // out bin l = P k + p, bins fastest
+    const float inv_scale = 1.f / map_scale(g.ms, mc, DT);
     for (int e = threadIdx.x; e < nrow * nd; e += kThreads) {
         const int r = e >> g.log2_nd, l = e & (nd - 1);
         const int k = l >> log2pd, p = l & (pd - 1);
-        rows[(size_t)r * nd + l] = cmul(buf[(r * pd + p) * stride + k], cen[k]);
+        const float2 v = cmul(buf[(r * pd + p) * stride + k], cen[k]);
+        char* row = rowb + (size_t)r * row_bytes;
+        if constexpr (DT == GH_MAP_C64) {
+            reinterpret_cast<float2*>(row)[l] = v;
+        } else {
+            reinterpret_cast<uint32_t*>(row)[l] =
+                float_to_half_bits(v.x * inv_scale, DT) | (float_to_half_bits(v.y * inv_scale, DT) << 16);
+        }
     }
 }
 
 }  // namespace
 
-hipError_t launch_rd_maps(const Geom& g, const float2* y, float2* maps, hipStream_t st) {
+hipError_t launch_rd_maps(const Geom& g, const float2* y, void* maps_v, int map_dtype, hipStream_t st) {
+    char* maps = static_cast<char*>(maps_v);
+    const size_t row_bytes = (size_t)g.nd * map_elem_bytes(map_dtype);
     // range pass: chirps per workgroup, halved (down to 8) until there are >= 512 workgroups
     int nch = kBuf / g.ms;
     if (nch > g.mc) nch = g.mc;
     while (nch > 8 && (long)(g.mc / nch) * g.pr * g.k < 512) nch >>= 1;
     const size_t lds1 = ((size_t)nch * (g.ms + 1) + 3 * (size_t)g.ms) * sizeof(float2);
-    hipLaunchKernelGGL(range_pass, dim3(g.mc / nch, g.pr, g.k), dim3(kThreads), lds1, st, g, nch, y, maps);
+    hipLaunchKernelGGL(range_pass, dim3(g.mc / nch, g.pr, g.k), dim3(kThreads), lds1, st, g, nch, row_bytes, y, maps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int nrow = kBuf / g.nd;
@@ -226,7 +246,13 @@ hipError_t launch_rd_maps(const Geom& g, const float2* y, float2* maps, hipStrea
     size_t lds2 = ((size_t)nrow * g.pd * (g.mc + 1) + 2 * (size_t)g.mc) * sizeof(float2);
     const int pre_lds = lds2 + (size_t)g.nd * sizeof(float2) <= 65536 ? 1 : 0;
     if (pre_lds) lds2 += (size_t)g.nd * sizeof(float2);
-    hipLaunchKernelGGL(doppler_pass, dim3(g.nr / nrow, g.k), dim3(kThreads), lds2, st, g, nrow, pre_lds, maps);
+    const dim3 grid2(g.nr / nrow, g.k);
+    if (map_dtype == GH_MAP_F16)
+        hipLaunchKernelGGL(doppler_pass<GH_MAP_F16>, grid2, dim3(kThreads), lds2, st, g, nrow, pre_lds, maps);
+    else if (map_dtype == GH_MAP_BF16)
+        hipLaunchKernelGGL(doppler_pass<GH_MAP_BF16>, grid2, dim3(kThreads), lds2, st, g, nrow, pre_lds, maps);
+    else
+        hipLaunchKernelGGL(doppler_pass<GH_MAP_C64>, grid2, dim3(kThreads), lds2, st, g, nrow, pre_lds, maps);
     return hipGetLastError();
 }
 

@@ -38,17 +38,20 @@ struct LocGeo {
     uint32_t ay;   // increment per vy grid step
 };
 
-__device__ __forceinline__ float2 map_row_value(const float2* __restrict__ mq, const Geom& g, int row, int l) {
-    // value of (unwrapped) range row `row` at Doppler bin l in [0, N_d)
+template <int DT>
+__device__ __forceinline__ float2 map_row_value(const char* __restrict__ mq, const Geom& g, int row, int l) {
+    // value of (unwrapped) range row `row` at Doppler bin l in [0, N_d), storage scale undone
     int wraps = row >> g.log2_nr;                  // floor division (arithmetic shift)
     int r = row & (g.nr - 1);
-    float2 v = mq[(size_t)r * g.nd + l];
-    if (wraps & 1) v = cscale(v, g.sign_r);
+    float2 v = map_ld1<DT>(mq, (uint32_t)(((size_t)r * g.nd + l) * map_elem_bytes(DT)));
+    const float sc = map_scale(g.ms, g.mc, DT);
+    if (wraps & 1) v = cscale(v, g.sign_r * sc);
+    else if (DT != GH_MAP_C64) v = cscale(v, sc);
     return v;
 }
 
-template <int INTERP>
-__global__ __launch_bounds__(kThreads) void gh_sweep_kernel(Geom g, GridP gp, const float2* __restrict__ maps,
+template <int INTERP, int DT>
+__global__ __launch_bounds__(kThreads) void gh_sweep_kernel(Geom g, GridP gp, const char* __restrict__ maps,
                                                            float* __restrict__ dec, gh_peak* __restrict__ block,
                                                            const int64_t* __restrict__ excl, int nexcl) {
     extern __shared__ float4 lds[];
@@ -93,7 +96,7 @@ __global__ __launch_bounds__(kThreads) void gh_sweep_kernel(Geom g, GridP gp, co
     const int shift = 32 - g.log2_nd;
     for (int q = 0; q < g.k; ++q) {
         const LocGeo lg = geo[q];
-        const float2* mq = maps + (size_t)q * g.nr * g.nd;
+        const char* mq = maps + (size_t)q * g.nr * g.nd * map_elem_bytes(DT);
         // range interpolation: Doppler profile of this location
         const float a = lg.a;
         float wr[4];
@@ -111,7 +114,7 @@ __global__ __launch_bounds__(kThreads) void gh_sweep_kernel(Geom g, GridP gp, co
             float2 h = make_float2(0.f, 0.f);
 #pragma unroll
             for (int t = 0; t < (INTERP ? 4 : 2); ++t) {
-                const float2 z = map_row_value(mq, g, lg.i0 + t, l);
+                const float2 z = map_row_value<DT>(mq, g, lg.i0 + t, l);
                 h.x += wr[t] * z.x;
                 h.y += wr[t] * z.y;
             }
@@ -226,9 +229,21 @@ __global__ __launch_bounds__(1024) void peak_final_kernel(const gh_peak* __restr
     }
 }
 
+template <int DT>
+void launch_generic(const Geom& g, const GridP& gp, const char* maps, int interp, float* dec, gh_peak* block,
+                    const int64_t* excl, int nexcl, hipStream_t st) {
+    const size_t lds = (size_t)g.nd * (interp ? 32 : 16) + (size_t)g.nd * 8;
+    if (interp == GH_INTERP_BICUBIC)
+        hipLaunchKernelGGL((gh_sweep_kernel<1, DT>), dim3(gp.nloc), dim3(kThreads), lds, st, g, gp, maps, dec, block,
+                           excl, nexcl);
+    else
+        hipLaunchKernelGGL((gh_sweep_kernel<0, DT>), dim3(gp.nloc), dim3(kThreads), lds, st, g, gp, maps, dec, block,
+                           excl, nexcl);
+}
+
 }  // namespace
 
-hipError_t launch_gh_sweep(const Geom& g, const GridP& gp, const float2* maps, int interp, float* dec,
+hipError_t launch_gh_sweep(const Geom& g, const GridP& gp, const void* maps, int map_dtype, int interp, float* dec,
                            gh_peak* block, const int64_t* excl, int nexcl, hipStream_t st) {
     // GH_SWEEP_KERNEL = columns | generic restricts the variant (diagnostics and tuning)
     static const int only = [] {
@@ -239,14 +254,15 @@ hipError_t launch_gh_sweep(const Geom& g, const GridP& gp, const float2* maps, i
     int lpb = 0, log2nvy = 0;
     size_t lds_cols = 0;
     if ((only == 0 || only == 2) && sweep_columns_plan(g, gp, interp, lpb, log2nvy, lds_cols))
-        return launch_gh_sweep_columns(g, gp, lpb, log2nvy, lds_cols, maps, interp, dec, block, excl, nexcl, st);
-    const size_t lds = (size_t)g.nd * (interp ? 32 : 16) + (size_t)g.nd * 8;
-    if (interp == GH_INTERP_BICUBIC)
-        hipLaunchKernelGGL(gh_sweep_kernel<1>, dim3(gp.nloc), dim3(kThreads), lds, st, g, gp, maps, dec, block,
-                           excl, nexcl);
+        return launch_gh_sweep_columns(g, gp, lpb, log2nvy, lds_cols, maps, map_dtype, interp, dec, block, excl, nexcl,
+                                       st);
+    const char* m = static_cast<const char*>(maps);
+    if (map_dtype == GH_MAP_F16)
+        launch_generic<GH_MAP_F16>(g, gp, m, interp, dec, block, excl, nexcl, st);
+    else if (map_dtype == GH_MAP_BF16)
+        launch_generic<GH_MAP_BF16>(g, gp, m, interp, dec, block, excl, nexcl, st);
     else
-        hipLaunchKernelGGL(gh_sweep_kernel<0>, dim3(gp.nloc), dim3(kThreads), lds, st, g, gp, maps, dec, block,
-                           excl, nexcl);
+        launch_generic<GH_MAP_C64>(g, gp, m, interp, dec, block, excl, nexcl, st);
     return hipGetLastError();
 }
 

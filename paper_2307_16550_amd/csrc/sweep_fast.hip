@@ -29,6 +29,8 @@
 // unrolled to a compile-time height NVX (points beyond the slab are evaluated
 // on valid table entries and discarded) with its LDS reads issued in batches.
 // The volume and the block maxima are written once, after the last receiver.
+// Maps stored as 16-bit float pairs (Z / (Ms Mc)) are widened to FP32 in the
+// table build, with the storage scale folded into the range weights.
 #include <stdlib.h>
 
 #include "gh_internal.h"
@@ -47,20 +49,14 @@ struct FastGeo {
     uint32_t pad;
 };
 
-__device__ __forceinline__ float4 ld4(const char* base, uint32_t off) {
-    return *reinterpret_cast<const float4*>(base + off);
-}
-__device__ __forceinline__ float2 ld2(const char* base, uint32_t off) {
-    return *reinterpret_cast<const float2*>(base + off);
-}
 
 __device__ __forceinline__ float2 wsum2(float w0, float2 a, float w1, float2 b) {
     return make_float2(fmaf(w1, b.x, w0 * a.x), fmaf(w1, b.y, w0 * a.y));
 }
 
-template <int INTERP, int MODE, int NVX>
+template <int INTERP, int MODE, int NVX, int DT>
 __global__ __launch_bounds__(kThreads) void gh_sweep_columns(Geom g, GridP gp, int lpb, int log2nvy,
-                                                            const float2* __restrict__ maps, float* __restrict__ dec,
+                                                            const char* __restrict__ maps, float* __restrict__ dec,
                                                             gh_peak* __restrict__ block,
                                                             const int64_t* __restrict__ excl, int nexcl) {
     extern __shared__ float4 lds[];
@@ -68,6 +64,8 @@ __global__ __launch_bounds__(kThreads) void gh_sweep_columns(Geom g, GridP gp, i
     constexpr int kTaps = INTERP ? 4 : 2;
     const int nd = g.nd;
     const int log2nd = g.log2_nd;
+    constexpr int kEs = map_elem_bytes(DT);            // bytes per stored map value
+    const float scale = map_scale(g.ms, g.mc, DT);     // folded into the range weights
     float4* tables = lds;                              // [lpb][nd][kEntry]
     FastGeo* geo = reinterpret_cast<FastGeo*>(lds + (size_t)lpb * nd * kEntry);   // [lpb][K]
 
@@ -121,8 +119,8 @@ __global__ __launch_bounds__(kThreads) void gh_sweep_columns(Geom g, GridP gp, i
             }
             for (int u = 0; u < kTaps; ++u) {
                 const int row = i0 + u;
-                fg.row[u] = ((uint32_t)(row & (g.nr - 1)) << log2nd) * 8u;   // byte offset of the row
-                fg.w[u] = ((row >> g.log2_nr) & 1) ? g.sign_r * w[u] : w[u];
+                fg.row[u] = ((uint32_t)(row & (g.nr - 1)) << log2nd) * (uint32_t)kEs;   // byte offset of the row
+                fg.w[u] = (((row >> g.log2_nr) & 1) ? g.sign_r * w[u] : w[u]) * scale;
             }
             const double inv = 1.0 / ((MODE == 0) ? 512.0 : (double)nd);
             fg.t0 = cycles_to_fixed(g.kd * (wx * gp.lo[2] + wy * gp.lo[3]) * inv);
@@ -149,19 +147,19 @@ __global__ __launch_bounds__(kThreads) void gh_sweep_columns(Geom g, GridP gp, i
     float4 pa[kPre], pb[kPre];
     float2 pa2[kPre], pb2[kPre];
     auto prefetch = [&](int qq) {
-        const char* mqq = reinterpret_cast<const char*>(maps + (size_t)qq * g.nr * nd);
+        const char* mqq = maps + (size_t)qq * g.nr * nd * kEs;
         const FastGeo fq = geo[ll * g.k + qq];
 #pragma unroll
         for (int i = 0; i < kPre; ++i) {
             const int run = lane + 64 * i;
             if (i < rpl && run < runs) {
                 const int l0 = run * 2;
-                const uint32_t o0 = (uint32_t)l0 * 8u;
-                const uint32_t ohi = (l0 + 2 == nd) ? 0u : o0 + 16u;
-                pa[i] = ld4(mqq, fq.row[0] + o0);
-                pb[i] = ld4(mqq, fq.row[1] + o0);
-                pa2[i] = ld2(mqq, fq.row[0] + ohi);
-                pb2[i] = ld2(mqq, fq.row[1] + ohi);
+                const uint32_t o0 = (uint32_t)l0 * kEs;
+                const uint32_t ohi = (l0 + 2 == nd) ? 0u : o0 + 2u * kEs;
+                pa[i] = map_ld2<DT>(mqq, fq.row[0] + o0);
+                pb[i] = map_ld2<DT>(mqq, fq.row[1] + o0);
+                pa2[i] = map_ld1<DT>(mqq, fq.row[0] + ohi);
+                pb2[i] = map_ld1<DT>(mqq, fq.row[1] + ohi);
             }
         }
     };
@@ -170,7 +168,7 @@ __global__ __launch_bounds__(kThreads) void gh_sweep_columns(Geom g, GridP gp, i
     for (int q = 0; q < g.k; ++q) {
         // all lanes finished reading the previous receiver's table (in-order LDS per wave)
         __builtin_amdgcn_wave_barrier();
-        const char* mq = reinterpret_cast<const char*>(maps + (size_t)q * g.nr * nd);
+        const char* mq = maps + (size_t)q * g.nr * nd * kEs;
         const FastGeo fb = geo[ll * g.k + q];
         float4* tabl = tables + (size_t)ll * nd * kEntry;
         if (pipelined) {
@@ -196,21 +194,21 @@ __global__ __launch_bounds__(kThreads) void gh_sweep_columns(Geom g, GridP gp, i
             float4* tab = tabl + (size_t)l0 * kEntry;
             // profile values h[l0 - 1 .. l0 + 5]; indices past the period come from its start with sign sd
             const bool top = (l0 + kRun == nd);
-            const uint32_t ohi = top ? 0u : (uint32_t)(l0 + kRun) * 8u;
+            const uint32_t ohi = top ? 0u : (uint32_t)(l0 + kRun) * kEs;
             const float shi = top ? sd : 1.f;
-            const uint32_t o0 = (uint32_t)l0 * 8u;
+            const uint32_t o0 = (uint32_t)l0 * kEs;
             float2 h[kRun + 3];
             if (INTERP == 0) {
                 const float w0 = fb.w[0], w1 = fb.w[1];
 #pragma unroll
                 for (int u = 0; u < kRun / 2; ++u) {
-                    const float4 a = ld4(mq, fb.row[0] + o0 + 16u * u);
-                    const float4 b = ld4(mq, fb.row[1] + o0 + 16u * u);
+                    const float4 a = map_ld2<DT>(mq, fb.row[0] + o0 + 2u * kEs * u);
+                    const float4 b = map_ld2<DT>(mq, fb.row[1] + o0 + 2u * kEs * u);
                     h[2 * u + 1] = wsum2(w0, make_float2(a.x, a.y), w1, make_float2(b.x, b.y));
                     h[2 * u + 2] = wsum2(w0, make_float2(a.z, a.w), w1, make_float2(b.z, b.w));
                 }
-                const float2 a2 = ld2(mq, fb.row[0] + ohi);
-                const float2 b2 = ld2(mq, fb.row[1] + ohi);
+                const float2 a2 = map_ld1<DT>(mq, fb.row[0] + ohi);
+                const float2 b2 = map_ld1<DT>(mq, fb.row[1] + ohi);
                 h[kRun + 1] = wsum2(w0 * shi, a2, w1 * shi, b2);
 #pragma unroll
                 for (int u = 0; u < kRun; ++u) {
@@ -219,7 +217,7 @@ __global__ __launch_bounds__(kThreads) void gh_sweep_columns(Geom g, GridP gp, i
                 }
             } else {
                 const bool bottom = (l0 == 0);
-                const uint32_t olo = bottom ? (uint32_t)(nd - 1) * 8u : o0 - 8u;
+                const uint32_t olo = bottom ? (uint32_t)(nd - 1) * kEs : o0 - kEs;
                 const float slo = bottom ? sd : 1.f;
 #pragma unroll
                 for (int u = 0; u < kRun + 3; ++u) h[u] = make_float2(0.f, 0.f);
@@ -227,10 +225,10 @@ __global__ __launch_bounds__(kThreads) void gh_sweep_columns(Geom g, GridP gp, i
                 for (int tap = 0; tap < 4; ++tap) {
                     const uint32_t rb = fb.row[tap];
                     const float w = fb.w[tap];
-                    const float2 v0 = ld2(mq, rb + olo);
-                    const float4 v1 = ld4(mq, rb + o0);
-                    const float4 v2 = ld4(mq, rb + o0 + 16);
-                    const float4 v3 = ld4(mq, rb + ohi);
+                    const float2 v0 = map_ld1<DT>(mq, rb + olo);
+                    const float4 v1 = map_ld2<DT>(mq, rb + o0);
+                    const float4 v2 = map_ld2<DT>(mq, rb + o0 + 2u * kEs);
+                    const float4 v3 = map_ld2<DT>(mq, rb + ohi);
                     const float wl = w * slo, wh = w * shi;
                     h[0] = make_float2(fmaf(wl, v0.x, h[0].x), fmaf(wl, v0.y, h[0].y));
                     h[1] = make_float2(fmaf(w, v1.x, h[1].x), fmaf(w, v1.y, h[1].y));
@@ -344,26 +342,37 @@ __global__ __launch_bounds__(kThreads) void gh_sweep_columns(Geom g, GridP gp, i
     }
 }
 
-template <int INTERP, int MODE>
+template <int INTERP, int MODE, int DT>
 hipError_t launch_cols(int nvx_t, dim3 grid, dim3 threads, size_t lds, hipStream_t st, const Geom& g,
-                       const GridP& gp, int lpb, int log2nvy, const float2* maps, float* dec, gh_peak* block,
+                       const GridP& gp, int lpb, int log2nvy, const char* maps, float* dec, gh_peak* block,
                        const int64_t* excl, int nexcl) {
     if (nvx_t == 2)
-        hipLaunchKernelGGL((gh_sweep_columns<INTERP, MODE, 2>), grid, threads, lds, st, g, gp, lpb, log2nvy, maps, dec,
-                           block, excl, nexcl);
+        hipLaunchKernelGGL((gh_sweep_columns<INTERP, MODE, 2, DT>), grid, threads, lds, st, g, gp, lpb, log2nvy, maps,
+                           dec, block, excl, nexcl);
     else if (nvx_t == 4)
-        hipLaunchKernelGGL((gh_sweep_columns<INTERP, MODE, 4>), grid, threads, lds, st, g, gp, lpb, log2nvy, maps, dec,
-                           block, excl, nexcl);
+        hipLaunchKernelGGL((gh_sweep_columns<INTERP, MODE, 4, DT>), grid, threads, lds, st, g, gp, lpb, log2nvy, maps,
+                           dec, block, excl, nexcl);
     else if (nvx_t == 8)
-        hipLaunchKernelGGL((gh_sweep_columns<INTERP, MODE, 8>), grid, threads, lds, st, g, gp, lpb, log2nvy, maps, dec,
-                           block, excl, nexcl);
+        hipLaunchKernelGGL((gh_sweep_columns<INTERP, MODE, 8, DT>), grid, threads, lds, st, g, gp, lpb, log2nvy, maps,
+                           dec, block, excl, nexcl);
     else if (nvx_t == 16)
-        hipLaunchKernelGGL((gh_sweep_columns<INTERP, MODE, 16>), grid, threads, lds, st, g, gp, lpb, log2nvy, maps,
+        hipLaunchKernelGGL((gh_sweep_columns<INTERP, MODE, 16, DT>), grid, threads, lds, st, g, gp, lpb, log2nvy, maps,
                            dec, block, excl, nexcl);
     else
-        hipLaunchKernelGGL((gh_sweep_columns<INTERP, MODE, 32>), grid, threads, lds, st, g, gp, lpb, log2nvy, maps,
+        hipLaunchKernelGGL((gh_sweep_columns<INTERP, MODE, 32, DT>), grid, threads, lds, st, g, gp, lpb, log2nvy, maps,
                            dec, block, excl, nexcl);
     return hipGetLastError();
+}
+
+template <int DT>
+hipError_t launch_cols_dt(int interp, bool small, int nvx_t, dim3 grid, dim3 threads, size_t lds, hipStream_t st,
+                          const Geom& g, const GridP& gp, int lpb, int log2nvy, const char* maps, float* dec,
+                          gh_peak* block, const int64_t* excl, int nexcl) {
+    if (interp == GH_INTERP_BICUBIC)
+        return small ? launch_cols<1, 0, DT>(nvx_t, grid, threads, lds, st, g, gp, lpb, log2nvy, maps, dec, block, excl, nexcl)
+                     : launch_cols<1, 1, DT>(nvx_t, grid, threads, lds, st, g, gp, lpb, log2nvy, maps, dec, block, excl, nexcl);
+    return small ? launch_cols<0, 0, DT>(nvx_t, grid, threads, lds, st, g, gp, lpb, log2nvy, maps, dec, block, excl, nexcl)
+                 : launch_cols<0, 1, DT>(nvx_t, grid, threads, lds, st, g, gp, lpb, log2nvy, maps, dec, block, excl, nexcl);
 }
 
 }  // namespace
@@ -394,18 +403,22 @@ bool sweep_columns_plan(const Geom& g, const GridP& gp, int interp, int& lpb, in
 }
 
 hipError_t launch_gh_sweep_columns(const Geom& g, const GridP& gp, int lpb, int log2nvy, size_t lds,
-                                   const float2* maps, int interp, float* dec, gh_peak* block, const int64_t* excl,
-                                   int nexcl, hipStream_t st) {
+                                   const void* maps_v, int map_dtype, int interp, float* dec, gh_peak* block,
+                                   const int64_t* excl, int nexcl, hipStream_t st) {
+    const char* maps = static_cast<const char*>(maps_v);
     const int nblocks = (gp.nloc + lpb - 1) / lpb;
     const dim3 grid(nblocks), threads(lpb * 64);
     const int chunk = (gp.n[2] + (64 >> log2nvy) - 1) >> (6 - log2nvy);
     const int nvx_t = chunk <= 2 ? 2 : chunk <= 4 ? 4 : chunk <= 8 ? 8 : chunk <= 16 ? 16 : 32;
     const bool small = g.nd <= 512;
-    if (interp == GH_INTERP_BICUBIC)
-        return small ? launch_cols<1, 0>(nvx_t, grid, threads, lds, st, g, gp, lpb, log2nvy, maps, dec, block, excl, nexcl)
-                     : launch_cols<1, 1>(nvx_t, grid, threads, lds, st, g, gp, lpb, log2nvy, maps, dec, block, excl, nexcl);
-    return small ? launch_cols<0, 0>(nvx_t, grid, threads, lds, st, g, gp, lpb, log2nvy, maps, dec, block, excl, nexcl)
-                 : launch_cols<0, 1>(nvx_t, grid, threads, lds, st, g, gp, lpb, log2nvy, maps, dec, block, excl, nexcl);
+    if (map_dtype == GH_MAP_F16)
+        return launch_cols_dt<GH_MAP_F16>(interp, small, nvx_t, grid, threads, lds, st, g, gp, lpb, log2nvy, maps, dec,
+                                          block, excl, nexcl);
+    if (map_dtype == GH_MAP_BF16)
+        return launch_cols_dt<GH_MAP_BF16>(interp, small, nvx_t, grid, threads, lds, st, g, gp, lpb, log2nvy, maps,
+                                           dec, block, excl, nexcl);
+    return launch_cols_dt<GH_MAP_C64>(interp, small, nvx_t, grid, threads, lds, st, g, gp, lpb, log2nvy, maps, dec,
+                                      block, excl, nexcl);
 }
 
 }  // namespace gh

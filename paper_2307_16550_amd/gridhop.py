@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libgridhop.so")
 GH_OK, GH_EINVAL, GH_EUNSUPPORTED, GH_EHIP, GH_EWORKSPACE = 0, -1, -2, -3, -4
 BILINEAR, BICUBIC = 0, 1
 GEMM_F32, GEMM_BF16 = 0, 1
+MAP_C64, MAP_F16, MAP_BF16 = 0, 1, 2
 MAX_SUPPORT = 32
 
 EXPORTS = ("gh_abi_version", "gh_last_error", "gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_workspace_bytes",
@@ -63,8 +64,8 @@ def load():
     rp, gp_, pp = ctypes.POINTER(GhRadar), ctypes.POINTER(GhGrid), ctypes.c_void_p
     lib.gh_abi_version.restype = ctypes.c_int
     lib.gh_last_error.restype = ctypes.c_char_p
-    lib.gh_rd_maps.argtypes = [rp, vp, vp, vp]
-    lib.gh_decision.argtypes = [rp, gp_, vp, i32, vp, pp, pp, vp]
+    lib.gh_rd_maps.argtypes = [rp, vp, vp, i32, vp]
+    lib.gh_decision.argtypes = [rp, gp_, vp, i32, i32, vp, pp, pp, vp]
     lib.gh_argmax.argtypes = [pp, ctypes.c_int64, pp, vp]
     lib.gh_direct_workspace_bytes.argtypes = [rp, gp_, i32]
     lib.gh_direct_workspace_bytes.restype = sz
@@ -151,20 +152,38 @@ def _c64(t):
     return t
 
 
-def rd_maps(radar: Radar, y: torch.Tensor, maps: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+_MAP_TORCH = {MAP_C64: torch.complex64, MAP_F16: torch.float16, MAP_BF16: torch.bfloat16}
+
+
+def map_dtype_of(maps: torch.Tensor) -> int:
+    """Storage code of a map tensor: complex64 [K, N_r, N_d], or float16 / bfloat16
+    [K, N_r, N_d, 2] holding Z / (Ms * Mc)."""
+    for code, dt in _MAP_TORCH.items():
+        if maps.dtype == dt:
+            if code != MAP_C64 and (maps.dim() != 4 or maps.shape[-1] != 2):
+                raise ValueError("16-bit maps must have shape [K, N_r, N_d, 2]")
+            if not maps.is_contiguous():
+                raise ValueError("maps must be contiguous")
+            return code
+    raise ValueError(f"unsupported map dtype {maps.dtype}")
+
+
+def rd_maps(radar: Radar, y: torch.Tensor, maps: torch.Tensor | None = None, map_dtype=MAP_C64,
+            stream=None) -> torch.Tensor:
     lib = load()
     _c64(y)
     if maps is None:
-        maps = torch.empty((radar.k, radar.nr, radar.nd), dtype=torch.complex64, device=y.device)
-    _c64(maps)
-    _check(lib.gh_rd_maps(ctypes.byref(radar.c_struct), _ptr(y), _ptr(maps), _stream(stream)))
+        shape = (radar.k, radar.nr, radar.nd) if map_dtype == MAP_C64 else (radar.k, radar.nr, radar.nd, 2)
+        maps = torch.empty(shape, dtype=_MAP_TORCH[map_dtype], device=y.device)
+    code = map_dtype_of(maps)
+    _check(lib.gh_rd_maps(ctypes.byref(radar.c_struct), _ptr(y), _ptr(maps), code, _stream(stream)))
     return maps
 
 
 def decision(radar: Radar, grid: GhGrid, maps, interp=BILINEAR, dec=None, block=None, argmax=None,
              write_volume=True, want_argmax=True, stream=None):
     lib = load()
-    _c64(maps)
+    code = map_dtype_of(maps)
     nloc = grid.n[0] * grid.n[1]
     if dec is None and write_volume:
         dec = torch.empty(tuple(grid.n), dtype=torch.float32, device=maps.device)
@@ -172,8 +191,8 @@ def decision(radar: Radar, grid: GhGrid, maps, interp=BILINEAR, dec=None, block=
         block = peaks_tensor(nloc, maps.device)
     if argmax is None and want_argmax:
         argmax = peaks_tensor(1, maps.device)
-    _check(lib.gh_decision(ctypes.byref(radar.c_struct), ctypes.byref(grid), _ptr(maps), int(interp), _ptr(dec),
-                           _ptr(block), _ptr(argmax), _stream(stream)))
+    _check(lib.gh_decision(ctypes.byref(radar.c_struct), ctypes.byref(grid), _ptr(maps), code, int(interp),
+                           _ptr(dec), _ptr(block), _ptr(argmax), _stream(stream)))
     return dec, block, argmax
 
 

@@ -56,19 +56,19 @@ FAKE = ctypes.c_void_p(0x1000)     # never dereferenced: validation fails first
 ])
 def test_invalid_radar_rejected(lib, field, value):
     r = radar(**{field: value})
-    rc = lib.gh_rd_maps(ctypes.byref(r.c_struct), FAKE, ctypes.c_void_p(0x100000000), None)
+    rc = lib.gh_rd_maps(ctypes.byref(r.c_struct), FAKE, ctypes.c_void_p(0x100000000), 0, None)
     assert rc == gh.GH_EINVAL
     assert gh.last_error()
 
 
 def test_null_and_overlap_rejected(lib):
     r = radar()
-    assert lib.gh_rd_maps(None, FAKE, FAKE, None) == gh.GH_EINVAL
-    assert lib.gh_rd_maps(ctypes.byref(r.c_struct), None, FAKE, None) == gh.GH_EINVAL
-    assert lib.gh_rd_maps(ctypes.byref(r.c_struct), FAKE, FAKE, None) == gh.GH_EINVAL
+    assert lib.gh_rd_maps(None, FAKE, FAKE, 0, None) == gh.GH_EINVAL
+    assert lib.gh_rd_maps(ctypes.byref(r.c_struct), None, FAKE, 0, None) == gh.GH_EINVAL
+    assert lib.gh_rd_maps(ctypes.byref(r.c_struct), FAKE, FAKE, 0, None) == gh.GH_EINVAL
     assert "overlap" in gh.last_error()
     r.c_struct.rx = None
-    assert lib.gh_rd_maps(ctypes.byref(r.c_struct), FAKE, ctypes.c_void_p(0x100000000), None) == gh.GH_EINVAL
+    assert lib.gh_rd_maps(ctypes.byref(r.c_struct), FAKE, ctypes.c_void_p(0x100000000), 0, None) == gh.GH_EINVAL
 
 
 @pytest.mark.parametrize("lo,hi,n", [
@@ -80,14 +80,14 @@ def test_null_and_overlap_rejected(lib):
 def test_invalid_grid_rejected(lib, lo, hi, n):
     r = radar()
     g = gh.make_grid(lo, hi, n)
-    rc = lib.gh_decision(ctypes.byref(r.c_struct), ctypes.byref(g), FAKE, 0, None, FAKE, None, None)
+    rc = lib.gh_decision(ctypes.byref(r.c_struct), ctypes.byref(g), FAKE, 0, 0, None, FAKE, None, None)
     assert rc in (gh.GH_EINVAL, gh.GH_EUNSUPPORTED)
 
 
 def test_decision_argument_checks(lib):
     r = radar()
-    assert lib.gh_decision(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, 7, None, FAKE, None, None) == gh.GH_EINVAL
-    assert lib.gh_decision(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, 0, None, None, None, None) == gh.GH_EINVAL
+    assert lib.gh_decision(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, 0, 7, None, FAKE, None, None) == gh.GH_EINVAL
+    assert lib.gh_decision(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, 0, 0, None, None, None, None) == gh.GH_EINVAL
 
 
 def test_workspace_queries_and_shortfall(lib):
@@ -121,7 +121,7 @@ def test_bomp_and_refine_argument_checks(lib):
 
 def test_error_message_cleared_after_success(lib):
     r = radar()
-    lib.gh_rd_maps(None, FAKE, FAKE, None)
+    lib.gh_rd_maps(None, FAKE, FAKE, 0, None)
     assert gh.last_error()
     assert lib.gh_refine(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, FAKE, 0, 20, None, 0, FAKE, None) == gh.GH_OK
     assert gh.last_error() == ""
@@ -131,11 +131,25 @@ def test_misaligned_pointers_rejected(lib):
     r = radar()
     odd = ctypes.c_void_p(0x1008)      # 8-byte aligned only
     far = ctypes.c_void_p(0x100000000)
-    assert lib.gh_rd_maps(ctypes.byref(r.c_struct), odd, far, None) == gh.GH_EINVAL
+    assert lib.gh_rd_maps(ctypes.byref(r.c_struct), odd, far, 0, None) == gh.GH_EINVAL
     assert "aligned" in gh.last_error()
-    assert lib.gh_decision(ctypes.byref(r.c_struct), ctypes.byref(GRID), odd, 0, None, FAKE, None, None) == gh.GH_EINVAL
+    assert lib.gh_decision(ctypes.byref(r.c_struct), ctypes.byref(GRID), odd, 0, 0, None, FAKE, None, None) == gh.GH_EINVAL
     need = lib.gh_direct_workspace_bytes(ctypes.byref(r.c_struct), ctypes.byref(GRID), 1)
     assert lib.gh_direct_decision(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, 1, odd, need, None, FAKE,
                                   None, None) == gh.GH_EINVAL
     assert lib.gh_refine(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, odd, 1, 20, FAKE, 1 << 20, FAKE,
                          None) == gh.GH_EINVAL
+
+
+def test_map_storage_checks(lib):
+    r = radar()
+    far = ctypes.c_void_p(0x100000000)
+    assert lib.gh_rd_maps(ctypes.byref(r.c_struct), FAKE, far, 3, None) == gh.GH_EINVAL
+    assert lib.gh_decision(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, -1, 0, None, FAKE, None, None) == gh.GH_EINVAL
+    r1 = radar(pad_doppler=1)
+    for dt in (gh.MAP_F16, gh.MAP_BF16):
+        assert lib.gh_rd_maps(ctypes.byref(r1.c_struct), FAKE, far, dt, None) == gh.GH_EUNSUPPORTED
+        assert "pad_doppler" in gh.last_error()
+        assert lib.gh_decision(ctypes.byref(r1.c_struct), ctypes.byref(GRID), FAKE, dt, 0, None, FAKE, None,
+                               None) == gh.GH_EUNSUPPORTED
+

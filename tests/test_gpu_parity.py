@@ -390,3 +390,107 @@ def test_refine_shapes(ms, mc, k, n):
     tr = orefine.refine(s.y, r, grid, [cell])
     assert np.max(np.abs(tg - tr)) <= 1e-3, (tg, tr)
 
+
+
+# ---------------------------------------------------------------- 16-bit map storage (precision axis)
+
+HALF_TOL = {gh.MAP_F16: 2e-3, gh.MAP_BF16: 1e-2}    # map and decision bars per storage type
+
+
+def half_maps_complex(z, radar):
+    """complex128 maps from a 16-bit [K, N_r, N_d, 2] tensor (stored scale Z / (Ms Mc) undone)."""
+    a = z.float().cpu().numpy().astype(np.float64)
+    return (a[..., 0] + 1j * a[..., 1]) * (radar.c_struct.n_samples * radar.c_struct.n_chirps)
+
+
+@pytest.mark.parametrize("dtype", [gh.MAP_F16, gh.MAP_BF16])
+@pytest.mark.parametrize("cfg", [1, 2, 3, 5])
+def test_rd_maps_half_storage(cfg, dtype):
+    say(f"rd_maps half cfg={cfg} dtype={dtype}")
+    s, r, gr = scene_and_radar(cfg)
+    z = gh.rd_maps(gr, to_dev(s.y), map_dtype=dtype)
+    zg = half_maps_complex(z, gr)
+    zr = omaps.rd_maps(s.y, r.pad_r, r.pad_d, r.centered)
+    errs = [np.linalg.norm(zg[q] - zr[q]) / np.linalg.norm(zr[q]) for q in range(r.k)]
+    say(f"rd_maps half cfg={cfg} dtype={dtype}: max rel error {max(errs):.3g}")
+    assert max(errs) <= HALF_TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [gh.MAP_F16, gh.MAP_BF16])
+@pytest.mark.parametrize("interp", [gh.BILINEAR, gh.BICUBIC])
+def test_gh_decision_half_maps_cfg1(interp, dtype):
+    say(f"gh half maps cfg1 interp={interp} dtype={dtype}")
+    s, r, gr = scene_and_radar(1)
+    z = gh.rd_maps(gr, to_dev(s.y), map_dtype=dtype)
+    dec, block, arg = gh.decision(gr, gh.grid_of(s.grid), z, interp)
+    dg = dec.cpu().numpy().astype(np.float64)
+    zr = omaps.rd_maps(s.y, r.pad_r, r.pad_d, r.centered)
+    dr = ogh.gh_decision(zr, r, s.grid, interp)
+    err = np.max(np.abs(dg - dr)) / dr.max()
+    say(f"gh half maps cfg1 interp={interp} dtype={dtype}: max rel error {err:.3g}")
+    assert err <= HALF_TOL[dtype]
+    bv, _ = gh.decode_peaks(block)
+    assert np.array_equal(bv, dg.reshape(len(bv), -1).max(axis=1).astype(np.float32))
+    _, ai = gh.decode_peaks(arg)
+    ref_val, ref_idx = opeaks.global_peak(dr)
+    check_argmax(lambda i: dr.ravel()[i], int(ai[0]), ref_idx, ref_val, f"half {dtype}", HALF_TOL[dtype])
+
+
+@pytest.mark.parametrize("ms,mc,n", [(128, 256, (5, 6, 32, 32)), (64, 32, (3, 4, 33, 2)), (64, 32, (7, 5, 3, 9))])
+@pytest.mark.parametrize("dtype", [gh.MAP_F16, gh.MAP_BF16])
+def test_gh_half_maps_shapes(ms, mc, n, dtype):
+    """N_d above 512 (wide fixed point), short slabs, and the generic kernel, on 16-bit maps."""
+    say(f"gh half shapes ms={ms} mc={mc} n={n} dtype={dtype}")
+    s, r, gr = scene_and_radar(1, 8, ms=ms, mc=mc)
+    grid = sc.Grid((5.5, -9.0, -12.0, -11.0), (23.0, 9.5, 12.5, 11.0), n)
+    z = gh.rd_maps(gr, to_dev(s.y), map_dtype=dtype)
+    dec, _, _ = gh.decision(gr, gh.grid_of(grid), z, gh.BILINEAR)
+    dg = dec.cpu().numpy().astype(np.float64)
+    zr = omaps.rd_maps(s.y, r.pad_r, r.pad_d, r.centered)
+    dr = ogh.gh_decision(zr, r, grid, gh.BILINEAR)
+    assert np.max(np.abs(dg - dr)) / dr.max() <= HALF_TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [gh.MAP_F16, gh.MAP_BF16])
+def test_gh_half_maps_sampled_cfg3(dtype):
+    """The precision workload: 8 receivers, 256x256x32x32 grid, 16-bit maps."""
+    say(f"gh half maps cfg3 dtype={dtype}")
+    s, r, gr = scene_and_radar(3)
+    z = gh.rd_maps(gr, to_dev(s.y), map_dtype=dtype)
+    dec, _, arg = gh.decision(gr, gh.grid_of(s.grid), z, gh.BILINEAR)
+    dg = dec.cpu().numpy().ravel()
+    av, ai = gh.decode_peaks(arg)
+    assert int(ai[0]) == int(np.argmax(dg))
+    rng = np.random.default_rng(17)
+    nv = s.grid.n[2] * s.grid.n[3]
+    loc = int(ai[0]) // nv
+    idx = np.concatenate([rng.integers(0, dg.size, 3000), np.arange(loc * nv, (loc + 1) * nv),
+                          [true_cell(s, t) for t in range(s.pos.shape[0])]])
+    zr = omaps.rd_maps(s.y, r.pad_r, r.pad_d, r.centered)
+    pts = np.stack([ord_.grid_point(s.grid, int(i)) for i in idx])
+    ref = ogh.gh_points(zr, r, pts[:, 0], pts[:, 1], pts[:, 2], pts[:, 3], gh.BILINEAR)
+    err = np.max(np.abs(dg[idx] - ref)) / max(ref.max(), float(av[0]))
+    say(f"gh half maps cfg3 dtype={dtype}: sampled max rel error {err:.3g}")
+    assert err <= HALF_TOL[dtype]
+
+
+def test_direct_bf16_full_grid_cfg3():
+    """The BF16 matrix-core direct decision on the whole precision-workload grid (67M points)."""
+    say("direct bf16 cfg3 full grid")
+    s, r, gr = scene_and_radar(3)
+    dec, _, arg = gh.direct_decision(gr, gh.grid_of(s.grid), to_dev(s.y), gemm=gh.GEMM_BF16)
+    dg = dec.cpu().numpy().ravel()
+    av, ai = gh.decode_peaks(arg)
+    assert int(ai[0]) == int(np.argmax(dg))
+    rng = np.random.default_rng(23)
+    nv = s.grid.n[2] * s.grid.n[3]
+    loc = int(ai[0]) // nv
+    idx = np.concatenate([rng.integers(0, dg.size, 400), np.arange(loc * nv, loc * nv + 256)])
+    pts = np.stack([ord_.grid_point(s.grid, int(i)) for i in idx])
+    ref = odirect.direct_points(s.y, r, pts[:, 0], pts[:, 1], pts[:, 2], pts[:, 3])
+    err = np.max(np.abs(dg[idx] - ref)) / max(ref.max(), float(av[0]))
+    say(f"direct bf16 cfg3: sampled max rel error {err:.3g}")
+    assert err <= BF16_TOL
+    # the reported maximum is at least the decision at the target's grid cell (a grid point)
+    d_at = lambda i: float(odirect.direct_points(s.y, r, *ord_.grid_point(s.grid, int(i))))
+    assert d_at(int(ai[0])) >= (1.0 - BF16_TOL) * d_at(true_cell(s))
