@@ -126,6 +126,7 @@ __global__ __launch_bounds__(kThreads) void bomp_fit_kernel(Geom g, GridP gp, co
     __shared__ uint32_t frx[kMaxSupport], fdx[kMaxSupport];
     __shared__ dcplx rhs[kMaxSupport];
     __shared__ dcplx gram[kMaxSupport][kMaxSupport];
+    __shared__ dcplx z[kMaxSupport];
     const int q = blockIdx.x;
     const int tid = threadIdx.x;
     if (tid < nsel) {
@@ -164,7 +165,6 @@ __global__ __launch_bounds__(kThreads) void bomp_fit_kernel(Geom g, GridP gp, co
                 gram[i][j] = {s.x / d, s.y / d};
             }
         }
-        dcplx z[kMaxSupport];
         for (int i = 0; i < nsel; ++i) {
             dcplx s = rhs[i];
             for (int k = 0; k < i; ++k) {

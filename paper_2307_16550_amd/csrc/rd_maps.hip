@@ -28,8 +28,9 @@
 namespace gh {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;
 constexpr int kBuf = 4096;        // complex values of FFT work per workgroup
+constexpr int kBfly = kBuf / 2 / kThreads;   // butterflies per thread and stage, at most
 
 // exp(-j pi num / den) with the numerator reduced exactly modulo 2 den.
 __device__ __forceinline__ float2 expm_pi(long long num, int den) {
@@ -72,11 +73,11 @@ __device__ void lds_fft(float2* buf, int nseq, int stride, int log2m, const floa
         const int per_seq = m >> log2r;               // butterflies per sequence
         const int log2ps = log2m - log2r;
         const int nbf = nseq << log2ps;
-        // at most kBuf / 2 / kThreads = 8 butterflies per thread (static register indexing)
-        float2 v[8][4];
-        int dst[8];
+        // at most kBfly butterflies per thread (static register indexing)
+        float2 v[kBfly][4];
+        int dst[kBfly];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
+        for (int c = 0; c < kBfly; ++c) {
             const int b = threadIdx.x + c * kThreads;
             if (b < nbf) {
                 const int seq = b >> log2ps;
@@ -108,7 +109,7 @@ __device__ void lds_fft(float2* buf, int nseq, int stride, int log2m, const floa
         }
         __syncthreads();
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
+        for (int c = 0; c < kBfly; ++c) {
             const int b = threadIdx.x + c * kThreads;
             if (b < nbf) {
                 buf[dst[c]] = v[c][0];

@@ -179,16 +179,16 @@ __global__ __launch_bounds__(1024) void peak_final_kernel(const gh_peak* __restr
     __shared__ long long red_i[16];
     float bv = -INFINITY;
     long long bi = 0x7fffffffffffffffLL;
-    // eight independent loads in flight per thread, then their comparisons
-    for (int b0 = threadIdx.x; b0 < n; b0 += 8 * blockDim.x) {
-        gh_peak p[8];
+    // sixteen independent loads in flight per thread, then their comparisons
+    for (int b0 = threadIdx.x; b0 < n; b0 += 16 * blockDim.x) {
+        gh_peak p[16];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < 16; ++k) {
             const int b = b0 + k * (int)blockDim.x;
             if (b < n) p[k] = blk[b];
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < 16; ++k) {
             const int b = b0 + k * (int)blockDim.x;
             if (b < n && (p[k].value > bv || (p[k].value == bv && p[k].index < bi))) {
                 bv = p[k].value;
