@@ -16,6 +16,8 @@ Radar", Monnoyer et al.):
   peaks.py   block and global argmax of a decision volume (eqs. (5)-(6))
   bomp.py    one Block-OMP iteration (multi-target extension, Sec. VI)
   refine.py  off-grid Newton refinement of the direct decision
+  grad.py    decisions at continuous points with their gradients with respect
+             to (x, y, vx, vy) and the receiver positions
 
 Every function is pinned by tests in tests/test_oracle_*.py against closed
 forms, brute force on tiny inputs, invariants, or values the paper prints.
