@@ -209,6 +209,36 @@ int gh_refine(const gh_radar *radar, const gh_grid *grid, const void *d_y, const
               int32_t n_cells, int32_t max_iter, void *d_ws, size_t ws_bytes, double *d_theta,
               void *stream);
 
+/* Decisions at continuous points, with gradients (differentiation axis; not
+ * in the paper).  For each point theta = (x, y, vx, vy) (d_theta: double
+ * [n_points][4], device):
+ *   d_value[i]             D(theta_i)                       (double [n_points])
+ *   d_grad[i][a]           dD/dtheta_a                      (double [n_points][4]; NULL: not computed)
+ *   d_grad_rx[i][q][b]     dD/d(rx_q)_b, receiver positions (double [n_points][K][2]; NULL: not computed)
+ * from dD/dp = sum_q 2 Re(conj(c_q) dc_q/dp) through the sensing functions of
+ * eqs. (1)-(2).  1 <= n_points <= 65535 (0: nothing is enqueued).  A
+ * non-finite theta gives non-finite outputs. */
+
+/* Workspace of gh_direct_points in bytes (0 on invalid arguments). */
+size_t gh_direct_points_workspace_bytes(const gh_radar *radar, int32_t n_points);
+
+/* Direct decision at points (Sec. I and III, scalar products with the atoms of
+ * eq. (3)): c_q = sum_{m,s} Y_q[m][s] exp(-j 2 pi (f_r s + f_d m)) with the
+ * moments M_10, M_01 (sample- and chirp-weighted sums) for the gradient.
+ * d_y: complex64 frames.  FP32 per chirp, FP64 beyond. */
+int gh_direct_points(const gh_radar *radar, const void *d_y, const double *d_theta, int32_t n_points,
+                     double *d_value, double *d_grad, double *d_grad_rx, void *d_ws, size_t ws_bytes,
+                     void *stream);
+
+/* Grid-hopping decision at points (Sec. IV, eq. (7)): the interpolated map
+ * values I_q at (t_r, t_d) in FP64 coordinates (bilinear or Keys bicubic,
+ * periodic with the centring sign), with dI/dt from the kernel derivative
+ * (bilinear: piecewise constant, one-sided at map nodes).  d_maps: output of
+ * gh_rd_maps in storage map_dtype. */
+int gh_gh_points(const gh_radar *radar, const void *d_maps, int32_t map_dtype, int32_t interp,
+                 const double *d_theta, int32_t n_points, double *d_value, double *d_grad, double *d_grad_rx,
+                 void *stream);
+
 #ifdef __cplusplus
 }
 #endif

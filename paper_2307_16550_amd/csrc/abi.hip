@@ -308,4 +308,52 @@ int gh_refine(const gh_radar* radar, const gh_grid* grid, const void* d_y, const
     return ok();
 }
 
+size_t gh_direct_points_workspace_bytes(const gh_radar* radar, int32_t n_points) {
+    gh::Geom g;
+    if (make_geom(radar, g)) return 0;
+    if (n_points < 1 || n_points > 65535) {
+        fail(GH_EINVAL, "n_points must be in [1, 65535]");
+        return 0;
+    }
+    ok();
+    return align256(gh::direct_points_ws_bytes(g, n_points));
+}
+
+int gh_direct_points(const gh_radar* radar, const void* d_y, const double* d_theta, int32_t n_points, double* d_value,
+                     double* d_grad, double* d_grad_rx, void* d_ws, size_t ws_bytes, void* stream) {
+    gh::Geom g;
+    int rc = make_geom(radar, g);
+    if (rc) return rc;
+    if (n_points < 0 || n_points > 65535) return fail(GH_EINVAL, "n_points must be in [0, 65535]");
+    if (!d_y || !d_theta || !d_value) return fail(GH_EINVAL, "d_y, d_theta and d_value must be non-NULL");
+    if ((rc = check_aligned({d_y, d_theta, d_value, d_grad, d_grad_rx, d_ws}))) return rc;
+    if (n_points == 0) return ok();
+    if (!d_ws) return fail(GH_EINVAL, "d_ws must be non-NULL");
+    const size_t need = align256(gh::direct_points_ws_bytes(g, n_points));
+    if (ws_bytes < need) return fail(GH_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if ((rc = check_device())) return rc;
+    hipError_t e = gh::launch_direct_points(g, (const float2*)d_y, d_theta, n_points, d_ws, d_value, d_grad,
+                                            d_grad_rx, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gh_direct_points launch");
+    return ok();
+}
+
+int gh_gh_points(const gh_radar* radar, const void* d_maps, int32_t map_dtype, int32_t interp, const double* d_theta,
+                 int32_t n_points, double* d_value, double* d_grad, double* d_grad_rx, void* stream) {
+    gh::Geom g;
+    int rc = make_geom(radar, g);
+    if (rc || (rc = check_map_dtype(g, map_dtype))) return rc;
+    if (interp != GH_INTERP_BILINEAR && interp != GH_INTERP_BICUBIC)
+        return fail(GH_EINVAL, "interp must be GH_INTERP_BILINEAR or GH_INTERP_BICUBIC");
+    if (n_points < 0 || n_points > 65535) return fail(GH_EINVAL, "n_points must be in [0, 65535]");
+    if (!d_maps || !d_theta || !d_value) return fail(GH_EINVAL, "d_maps, d_theta and d_value must be non-NULL");
+    if ((rc = check_aligned({d_maps, d_theta, d_value, d_grad, d_grad_rx}))) return rc;
+    if (n_points == 0) return ok();
+    if ((rc = check_device())) return rc;
+    hipError_t e = gh::launch_gh_points(g, d_maps, map_dtype, interp, d_theta, n_points, d_value, d_grad, d_grad_rx,
+                                        (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gh_gh_points launch");
+    return ok();
+}
+
 }  // extern "C"

@@ -216,4 +216,10 @@ size_t refine_ws_bytes(const Geom& g, int ncells);
 hipError_t launch_refine(const Geom& g, const GridP& gp, const float2* y, const int64_t* cells, int ncells,
                          int max_iter, void* ws, double* theta, hipStream_t st);
 
+size_t direct_points_ws_bytes(const Geom& g, int npts);
+hipError_t launch_direct_points(const Geom& g, const float2* y, const double* theta, int npts, void* ws,
+                                double* value, double* grad, double* grad_rx, hipStream_t st);
+hipError_t launch_gh_points(const Geom& g, const void* maps, int map_dtype, int interp, const double* theta, int npts,
+                            double* value, double* grad, double* grad_rx, hipStream_t st);
+
 }  // namespace gh

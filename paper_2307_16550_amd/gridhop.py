@@ -25,7 +25,7 @@ MAX_SUPPORT = 32
 
 EXPORTS = ("gh_abi_version", "gh_last_error", "gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_workspace_bytes",
            "gh_direct_decision", "gh_bomp_workspace_bytes", "gh_bomp_step", "gh_refine_workspace_bytes",
-           "gh_refine")
+           "gh_refine", "gh_direct_points_workspace_bytes", "gh_direct_points", "gh_gh_points")
 
 
 class GhRadar(ctypes.Structure):
@@ -76,7 +76,12 @@ def load():
     lib.gh_refine_workspace_bytes.argtypes = [rp, gp_, i32]
     lib.gh_refine_workspace_bytes.restype = sz
     lib.gh_refine.argtypes = [rp, gp_, vp, vp, i32, i32, vp, sz, vp, vp]
-    for name in ("gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_decision", "gh_bomp_step", "gh_refine"):
+    lib.gh_direct_points_workspace_bytes.argtypes = [rp, i32]
+    lib.gh_direct_points_workspace_bytes.restype = sz
+    lib.gh_direct_points.argtypes = [rp, vp, vp, i32, vp, vp, vp, vp, sz, vp]
+    lib.gh_gh_points.argtypes = [rp, vp, i32, i32, vp, i32, vp, vp, vp, vp]
+    for name in ("gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_decision", "gh_bomp_step", "gh_refine",
+                 "gh_direct_points", "gh_gh_points"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -111,6 +116,12 @@ class Radar:
         self.c_struct = GhRadar(float(f0), float(bw), float(tc), float(c), self.ms, self.mc, self.pad_r, self.pad_d,
                                 self.k, int(centered), (ctypes.c_double * 2)(*[float(v) for v in tx]),
                                 self.rx.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+
+    def with_rx(self, rx) -> "Radar":
+        """The same radar with other receiver positions (K x 2, metres)."""
+        c = self.c_struct
+        return Radar(c.f0_hz, c.bandwidth_hz, c.t_chirp_s, self.ms, self.mc, (c.tx[0], c.tx[1]), rx, self.pad_r,
+                     self.pad_d, c.centered, c.c_mps)
 
     @property
     def nr(self):
@@ -288,3 +299,48 @@ def refine(radar: Radar, grid: GhGrid, y, cells: torch.Tensor, max_iter=20, thet
     _check(lib.gh_refine(ctypes.byref(radar.c_struct), ctypes.byref(grid), _ptr(y), _ptr(cells), cells.numel(),
                          int(max_iter), _ptr(ws), nws, _ptr(theta), _stream(stream)))
     return theta
+
+
+def _points_outputs(theta, k, want_grad, want_grad_rx):
+    if theta.dtype != torch.float64 or not theta.is_cuda or theta.dim() != 2 or theta.shape[1] != 4:
+        raise ValueError("theta must be a float64 CUDA tensor of shape [n, 4]")
+    theta = theta.contiguous()
+    n = theta.shape[0]
+    value = torch.empty(n, dtype=torch.float64, device=theta.device)
+    grad = torch.empty((n, 4), dtype=torch.float64, device=theta.device) if want_grad else None
+    grad_rx = torch.empty((n, k, 2), dtype=torch.float64, device=theta.device) if want_grad_rx else None
+    return theta, value, grad, grad_rx
+
+
+def direct_points(radar: Radar, y, theta: torch.Tensor, want_grad=True, want_grad_rx=False, ws=None, stream=None):
+    """Direct decision at continuous points theta [n, 4] (x, y, vx, vy): (value [n], grad [n, 4] or None,
+    grad_rx [n, K, 2] or None)."""
+    lib = load()
+    _c64(y)
+    theta, value, grad, grad_rx = _points_outputs(theta, radar.k, want_grad, want_grad_rx)
+    n = theta.shape[0]
+    if n == 0:
+        return value, grad, grad_rx
+    if ws is None:
+        nb = lib.gh_direct_points_workspace_bytes(ctypes.byref(radar.c_struct), n)
+        if nb == 0:
+            raise GridHopError(GH_EINVAL, last_error())
+        ws = torch.empty(nb, dtype=torch.uint8, device=theta.device)
+    _check(lib.gh_direct_points(ctypes.byref(radar.c_struct), _ptr(y), _ptr(theta), n, _ptr(value), _ptr(grad),
+                                _ptr(grad_rx), _ptr(ws), ws.numel(), _stream(stream)))
+    return value, grad, grad_rx
+
+
+def gh_points(radar: Radar, maps, theta: torch.Tensor, interp=BILINEAR, want_grad=True, want_grad_rx=False,
+              stream=None):
+    """Grid-hopping decision at continuous points theta [n, 4]: (value, grad or None, grad_rx or None)."""
+    lib = load()
+    code = map_dtype_of(maps)
+    theta, value, grad, grad_rx = _points_outputs(theta, radar.k, want_grad, want_grad_rx)
+    n = theta.shape[0]
+    if n == 0:
+        return value, grad, grad_rx
+    _check(lib.gh_gh_points(ctypes.byref(radar.c_struct), _ptr(maps), code, int(interp), _ptr(theta), n,
+                            _ptr(value), _ptr(grad), _ptr(grad_rx), _stream(stream)))
+    return value, grad, grad_rx
+

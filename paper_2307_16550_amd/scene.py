@@ -109,7 +109,7 @@ CONFIGS = {
     1: dict(k=3, ms=64, mc=32, targets=1, snr_db=20.0, n=(32, 32, 8, 8)),
     2: dict(k=4, ms=256, mc=128, targets=3, snr_db=10.0, n=(128, 128, 32, 32)),
     3: dict(k=8, ms=64, mc=32, targets=1, snr_db=20.0, n=(256, 256, 32, 32)),
-    5: dict(k=8, ms=512, mc=256, targets=8, snr_db=5.0, n=(128, 128, 32, 32)),
+    5: dict(k=8, ms=512, mc=256, targets=8, snr_db=5.0, n=(128, 128, 32, 32), close_pairs=2),
 }
 F0, BW, TC, PAD = 24e9, 250e6, 256e-6, 4
 
@@ -175,6 +175,12 @@ def make_scene(cfg: int = 1, trial: int = 0, seed: int | None = None, *, snr_db:
     for t in range(nt):
         pos[t] = rng.uniform(X_LO, X_HI)
         vel[t] = rng.uniform(V_LO, V_HI)
+    # targets 2p + 1 placed within one bistatic range cell (c / B = 1.2 m) of targets 2p
+    for pr in range(min(spec.get("close_pairs", 0), nt // 2)):
+        ang = rng.uniform(0.0, 2.0 * np.pi)
+        dist = rng.uniform(0.3, 0.9)
+        cand = pos[2 * pr] + dist * np.array([np.cos(ang), np.sin(ang)])
+        pos[2 * pr + 1] = np.clip(cand, X_LO, X_HI)
     alpha = (rng.standard_normal((nt, spec["k"])) + 1j * rng.standard_normal((nt, spec["k"]))) / math.sqrt(2.0)
     grid = full_grid(spec["n"])
     if on_grid:

@@ -153,3 +153,23 @@ def test_map_storage_checks(lib):
         assert lib.gh_decision(ctypes.byref(r1.c_struct), ctypes.byref(GRID), FAKE, dt, 0, None, FAKE, None,
                                None) == gh.GH_EUNSUPPORTED
 
+
+
+def test_point_decision_argument_checks(lib):
+    r = radar()
+    far = ctypes.c_void_p(0x100000000)
+    need = lib.gh_direct_points_workspace_bytes(ctypes.byref(r.c_struct), 16)
+    assert need >= 16 * 3 * (32 // 8) * 6 * 8
+    assert lib.gh_direct_points_workspace_bytes(ctypes.byref(r.c_struct), 0) == 0
+    assert lib.gh_direct_points_workspace_bytes(ctypes.byref(r.c_struct), 70000) == 0
+    args = [ctypes.byref(r.c_struct), FAKE, far]
+    assert lib.gh_direct_points(*args, 16, FAKE, None, None, FAKE, need - 1, None) == gh.GH_EWORKSPACE
+    assert lib.gh_direct_points(*args, -1, FAKE, None, None, FAKE, need, None) == gh.GH_EINVAL
+    assert lib.gh_direct_points(*args, 16, None, None, None, FAKE, need, None) == gh.GH_EINVAL
+    assert lib.gh_direct_points(*args, 0, FAKE, None, None, None, 0, None) == gh.GH_OK
+    margs = [ctypes.byref(r.c_struct), FAKE, 0]
+    assert lib.gh_gh_points(*margs, 2, far, 4, FAKE, None, None, None) == gh.GH_EINVAL          # interp
+    assert lib.gh_gh_points(ctypes.byref(r.c_struct), FAKE, 5, 0, far, 4, FAKE, None, None, None) == gh.GH_EINVAL
+    assert lib.gh_gh_points(*margs, 0, far, 70000, FAKE, None, None, None) == gh.GH_EINVAL
+    assert lib.gh_gh_points(*margs, 0, far, 0, FAKE, None, None, None) == gh.GH_OK
+    assert lib.gh_gh_points(*margs, 0, ctypes.c_void_p(0x100000008), 4, FAKE, None, None, None) == gh.GH_EINVAL
