@@ -22,6 +22,12 @@ per launch are the FP32 volume write, one read of the four maps and the block
 maxima.  The CPU baseline runs the FP64 numpy oracle in a child process on a
 bounded sample of the same frame, one thread, and scales its per-point rates
 to the step.
+
+Beside the step (not part of `value`), the batching workload is measured: 64
+seeded frames of mixed shapes (K 3..8, Ms 128/256, Mc 64/128, grids 64^2..192^2
+x 16^2..32^2) through the batch entry points (maps, bilinear decision with
+block maxima, per-frame argmax; three persistent launches plus the argmax),
+launch shapes autotuned, one run captured in a HIP graph and replayed.
 """
 from __future__ import annotations
 
@@ -40,7 +46,9 @@ CFG = 2
 HBM_PEAK_GBS = 8000.0
 BOMP_ITERS = 3
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "gh_sweep_columns_paper_scale_hbm_traffic.md")
-SWEEP_SOURCES = [os.path.join(ROOT, "paper_2307_16550_amd", "csrc", f) for f in ("sweep_fast.hip", "gh_internal.h")]
+SWEEP_SOURCES = [os.path.join(ROOT, "paper_2307_16550_amd", "csrc", f)
+                 for f in ("sweep_fast.hip", "sweep_table.h", "gh_internal.h")]
+BATCH_REPLAYS = 10
 
 
 def recorded_traffic():
@@ -69,6 +77,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batching-workload measurement")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only measure the batching workload and print its JSON object (profiling)")
     ap.add_argument("--interp", choices=["bilinear", "bicubic"], default="bilinear")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this size (HBM counter calibration) and exit")
@@ -164,6 +175,32 @@ def cpu_baseline(job):
 
 # ----------------------------------------------------------------------------- GPU benchmark
 
+def batch_workload(gh, sc, torch, stream):
+    """Frames/s and grid points/s of the batching workload (graph replays, HIP events)."""
+    scenes = sc.make_batch()
+    b = gh.Batch.from_scenes(scenes, gh.BILINEAR)
+    tuned = gh.autotune(b, reps=3)
+    g = b.capture()
+    g.replay()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(BATCH_REPLAYS):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / BATCH_REPLAYS
+    info = b.info()
+    b.close()
+    return {"workload": "64 seeded frames of mixed shapes, bilinear, maps + decision (block maxima) + argmax",
+            "frames": info["n_frames"], "points": info["points"], "ms_per_batch": ms,
+            "frames_per_s": info["n_frames"] / ms * 1e3, "points_per_s": info["points"] / ms * 1e3,
+            "replays": BATCH_REPLAYS, "hip_graph": True,
+            "launch_shape": {"workgroups": info["workgroups"], "sweep_waves": info["sweep_waves"],
+                             "column_height": info["column_height"]},
+            "autotune_trials": len(tuned["trials"])}
+
+
 def main():
     args = parse()
     if args.cpu_worker:
@@ -190,6 +227,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_mib": args.copy_calibration_mib, "launches": 3}))
+        return 0
+
+    if args.batch_only:
+        print(json.dumps(batch_workload(gh, sc, torch, torch.cuda.current_stream())), flush=True)
         return 0
 
     interp = gh.BICUBIC if args.interp == "bicubic" else gh.BILINEAR
@@ -312,6 +353,9 @@ def main():
                      "algorithmic_bytes_per_launch": sweep_bytes,
                      "avg_launch_us": t_sweep * 1e6},
     }
+
+    if not args.no_batch:
+        line["batch"] = batch_workload(gh, sc, torch, stream)
 
     if not args.no_cpu_baseline:
         rng = np.random.default_rng(2024)

@@ -239,6 +239,81 @@ int gh_gh_points(const gh_radar *radar, const void *d_maps, int32_t map_dtype, i
                  const double *d_theta, int32_t n_points, double *d_value, double *d_grad, double *d_grad_rx,
                  void *stream);
 
+/* ---- Batches of frames (batching axis; not in the paper) -------------------
+ * Many frames of different shapes (radar, grid) decided together: their maps
+ * (gh_rd_maps), grid-hopping decisions (gh_decision) and per-frame argmax,
+ * each step as one persistent launch over all frames that reads a
+ * frame-descriptor table in device memory.  A gh_batch is a host object made
+ * once per batch layout; unlike every other entry point it RETAINS the frame
+ * and workspace pointers it was created with (until gh_batch_destroy), so a
+ * run only launches kernels and can be captured in a HIP graph and replayed:
+ * it enqueues no memset or copy and needs nothing reset between runs. */
+
+/* One frame of a batch.  radar->rx is read during gh_batch_create. */
+typedef struct {
+    gh_radar radar;
+    gh_grid grid;
+    const void *d_y;      /* complex64 [K][Mc][Ms] (read at every run) */
+    float *d_decision;    /* float volume of the frame's grid, or NULL (not written) */
+    gh_peak *d_block;     /* gh_peak [Nx*Ny] per-location maxima (required) */
+} gh_frame;
+
+typedef struct gh_batch gh_batch;   /* opaque */
+
+/* Launch shape of a batch (gh_batch_get_info). */
+typedef struct {
+    int32_t n_frames;
+    int32_t interp;
+    int32_t units[3];           /* work units of the range, Doppler and sweep launches */
+    int32_t workgroups[3];      /* persistent grid sizes in use (gh_batch_tune) */
+    int32_t max_workgroups[3];  /* workgroups resident at once (occupancy x compute units) */
+    int32_t sweep_waves;        /* waves per sweep workgroup: 1, 2 or 4 */
+    int32_t column_height;      /* compiled vx points per lane of the sweep */
+    int32_t reserved;
+    int64_t points;             /* grid points over all frames */
+    int64_t workspace_bytes;    /* bytes of the workspace the batch uses */
+} gh_batch_info;
+
+/* Workspace of a batch in bytes: the descriptor table and every frame's
+ * complex64 maps.  0 on invalid frames (see gh_last_error). */
+size_t gh_batch_workspace_bytes(const gh_frame *frames, int32_t n_frames);
+
+/* Validate 1 <= n_frames <= 65535 frames (host array), lay out d_ws and upload
+ * the descriptor table on `stream`, then synchronise that stream once (this
+ * call blocks; gh_batch_run never does).  Per frame: the limits of gh_rd_maps
+ * and gh_decision, N_d >= 16, Nvy <= 64 and ceil(Nvx / floor(64 / Nvy)) <= 32
+ * (a lane's share of the velocity slab); the descriptor table plus the largest
+ * Doppler table must fit one wave's 64 KB LDS slice (GH_EUNSUPPORTED
+ * otherwise).  interp: GH_INTERP_* for every frame.  d_ws must hold
+ * gh_batch_workspace_bytes(); its contents belong to the batch until
+ * gh_batch_destroy.  *batch receives the new object (NULL on error). */
+int gh_batch_create(const gh_frame *frames, int32_t n_frames, int32_t interp, void *d_ws, size_t ws_bytes,
+                    gh_batch **batch, void *stream);
+
+/* Persistent grid sizes (the batch's tuning knobs): workgroups of the range,
+ * Doppler and sweep launches (0 keeps the current value; defaults: as many
+ * as are resident at once), and waves per sweep workgroup (1, 2 or 4; 0
+ * keeps).  Any positive count is correct; launches clamp to their units. */
+int gh_batch_tune(gh_batch *batch, int32_t range_workgroups, int32_t doppler_workgroups, int32_t sweep_workgroups,
+                  int32_t sweep_waves);
+
+int gh_batch_get_info(const gh_batch *batch, gh_batch_info *info);
+
+/* One pass over every frame: maps, decision (volume when d_decision was given,
+ * block maxima always) and d_argmax[f] = the frame's maximum (gh_peak
+ * [n_frames], ties to the lowest index; NULL: not computed).  Results equal
+ * gh_rd_maps + gh_decision + gh_argmax per frame.  Runs on the device the
+ * batch was created on. */
+int gh_batch_run(const gh_batch *batch, gh_peak *d_argmax, void *stream);
+
+/* Device address of frame f's complex64 maps [K][N_r][N_d] inside the batch
+ * workspace (valid after a run, until the next run overwrites them; for
+ * gh_gh_points or gh_decision on one frame). */
+int gh_batch_frame_maps(const gh_batch *batch, int32_t frame, void **d_maps);
+
+/* Free the host object (NULL is a no-op).  Work already enqueued is unaffected. */
+void gh_batch_destroy(gh_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,8 @@
 #include <string.h>
 
 #include <initializer_list>
+#include <new>
+#include <vector>
 
 #include "gh_internal.h"
 
@@ -142,6 +144,62 @@ int check_map_dtype(const gh::Geom& g, int dt) {
 int check_aligned(std::initializer_list<const void*> ptrs) {
     for (const void* p : ptrs)
         if (((uintptr_t)p & 15) != 0) return fail(GH_EINVAL, "device arrays must be 16-byte aligned");
+    return GH_OK;
+}
+
+}  // namespace
+
+// Host object of a batch of frames (include/gridhop.h).
+struct gh_batch {
+    int nf = 0, interp = 0, device = 0;
+    int units[3] = {0, 0, 0};
+    size_t lds1 = 0, lds2 = 0;   // LDS of the range and Doppler workgroups
+    int nvx_t = 0, wave_f4 = 0;  // sweep column height, float4 per wave slice
+    int waves = 4;
+    int wg[3] = {0, 0, 0};
+    int wg_max[3] = {0, 0, 0};
+    long long points = 0;
+    size_t ws_used = 0;
+    gh::FrameDesc* d_table = nullptr;
+    std::vector<gh::FrameDesc> table;   // host copy of the uploaded descriptors
+};
+
+namespace {
+
+// Prefix the current error message with the frame's number.
+int frame_fail(int rc, int f) {
+    char msg[sizeof(g_err)];
+    memcpy(msg, g_err, sizeof(msg));
+    return fail(rc, "frame %d: %s", f, msg);
+}
+
+int current_device(int& dev) {
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "no usable HIP device");
+    return GH_OK;
+}
+
+// Sizes of a batch's workspace: the table, then each frame's maps.
+int batch_layout(const gh_frame* frames, int nf, std::vector<gh::Geom>& gs, std::vector<gh::GridP>& gps,
+                 size_t& bytes) {
+    if (!frames) return fail(GH_EINVAL, "frames is NULL");
+    if (nf < 1 || nf > 65535) return fail(GH_EINVAL, "n_frames must be in [1, 65535]");
+    gs.resize(nf);
+    gps.resize(nf);
+    bytes = align256((size_t)nf * sizeof(gh::FrameDesc));
+    for (int f = 0; f < nf; ++f) {
+        int rc = make_geom(&frames[f].radar, gs[f]);
+        if (rc || (rc = make_grid(&frames[f].grid, gps[f]))) return frame_fail(rc, f);
+        bytes += align256((size_t)gs[f].k * gs[f].nr * gs[f].nd * 8);
+    }
+    return GH_OK;
+}
+
+int check_waves(int waves, int wave_f4) {
+    if (waves != 1 && waves != 2 && waves != 4) return fail(GH_EINVAL, "sweep_waves must be 1, 2 or 4");
+    if ((size_t)waves * wave_f4 * 16 > 65536)
+        return fail(GH_EUNSUPPORTED, "%d sweep waves need %zu bytes of LDS (limit 65536)", waves,
+                    (size_t)waves * wave_f4 * 16);
     return GH_OK;
 }
 
@@ -355,5 +413,186 @@ int gh_gh_points(const gh_radar* radar, const void* d_maps, int32_t map_dtype, i
     if (e != hipSuccess) return hip_fail(e, "gh_gh_points launch");
     return ok();
 }
+
+size_t gh_batch_workspace_bytes(const gh_frame* frames, int32_t n_frames) {
+    std::vector<gh::Geom> gs;
+    std::vector<gh::GridP> gps;
+    size_t bytes = 0;
+    if (batch_layout(frames, n_frames, gs, gps, bytes)) return 0;
+    ok();
+    return bytes;
+}
+
+int gh_batch_create(const gh_frame* frames, int32_t n_frames, int32_t interp, void* d_ws, size_t ws_bytes,
+                    gh_batch** batch, void* stream) {
+    if (!batch) return fail(GH_EINVAL, "batch is NULL");
+    *batch = nullptr;
+    std::vector<gh::Geom> gs;
+    std::vector<gh::GridP> gps;
+    size_t need = 0;
+    int rc = batch_layout(frames, n_frames, gs, gps, need);
+    if (rc) return rc;
+    if (interp != GH_INTERP_BILINEAR && interp != GH_INTERP_BICUBIC)
+        return fail(GH_EINVAL, "interp must be GH_INTERP_BILINEAR or GH_INTERP_BICUBIC");
+    if (!d_ws) return fail(GH_EINVAL, "d_ws is NULL");
+    if ((rc = check_aligned({d_ws}))) return rc;
+    if (ws_bytes < need) return fail(GH_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    int nd_max = 0, chunk_max = 0;
+    long long units[3] = {0, 0, 0}, points = 0;
+    std::vector<gh::FrameDesc> table(n_frames);
+    char* maps = (char*)d_ws + align256((size_t)n_frames * sizeof(gh::FrameDesc));
+    size_t lds1 = 0, lds2 = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        const gh_frame& fr = frames[f];
+        const gh::Geom& g = gs[f];
+        const gh::GridP& gp = gps[f];
+        if (!fr.d_y || !fr.d_block) return fail(GH_EINVAL, "frame %d: d_y and d_block must be non-NULL", f);
+        if ((rc = check_aligned({fr.d_y, fr.d_decision, fr.d_block}))) return frame_fail(rc, f);
+        if (g.nd < 16) return fail(GH_EUNSUPPORTED, "frame %d: N_d = %d < 16", f, g.nd);
+        const int nvy = gp.n[3];
+        if (nvy > 64) return fail(GH_EUNSUPPORTED, "frame %d: Nvy = %d > 64", f, nvy);
+        const int parts = 64 / nvy;
+        const int chunk = (gp.n[2] + parts - 1) / parts;
+        if (chunk > 32) return fail(GH_EUNSUPPORTED, "frame %d: %d vx points per lane (limit 32)", f, chunk);
+        gh::FrameDesc& d = table[f];
+        memset(&d, 0, sizeof(d));
+        d.g = g;
+        d.gp = gp;
+        d.y = (const float2*)fr.d_y;
+        d.maps = maps;
+        d.dec = fr.d_decision;
+        d.block = fr.d_block;
+        size_t l1, l2;
+        gh::rd_maps_plan(g, d.nch, l1, d.nrow, d.pre_lds, l2);
+        lds1 = l1 > lds1 ? l1 : lds1;
+        lds2 = l2 > lds2 ? l2 : lds2;
+        d.nunit[0] = g.k * g.pr * (g.mc / d.nch);
+        d.nunit[1] = g.k * (g.nr / d.nrow);
+        d.nunit[2] = gp.nloc;
+        for (int w = 0; w < 3; ++w) {
+            d.unit0[w] = (int)units[w];
+            units[w] += d.nunit[w];
+        }
+        d.nvy = nvy;
+        d.parts = parts;
+        d.chunk = chunk;
+        nd_max = g.nd > nd_max ? g.nd : nd_max;
+        chunk_max = chunk > chunk_max ? chunk : chunk_max;
+        points += (long long)gp.nloc * gp.nv;
+        maps += align256((size_t)g.k * g.nr * g.nd * 8);
+    }
+    for (int w = 0; w < 3; ++w)
+        if (units[w] >= (1LL << 31)) return fail(GH_EUNSUPPORTED, "batch has more than 2^31 work units");
+    // the map passes of a batch also hold the current frame's descriptor in LDS
+    if (lds1 + sizeof(gh::FrameDesc) > 65536 || lds2 + sizeof(gh::FrameDesc) > 65536)
+        return fail(GH_EUNSUPPORTED, "map passes of this batch need more than 64 KB of LDS");
+    const int wave_f4 = gh::sweep_batch_slice_f4(interp, nd_max);
+    int nvx_t = 0;
+    gh::sweep_batch_nvx(chunk_max, nvx_t);
+    int waves = 4;
+    while (waves > 1 && (size_t)waves * wave_f4 * 16 > 65536) waves >>= 1;
+    int device = 0;
+    if ((rc = check_waves(waves, wave_f4)) || (rc = current_device(device))) return rc;
+    gh_batch* b = new (std::nothrow) gh_batch;
+    if (!b) return fail(GH_EINVAL, "out of host memory");
+    b->device = device;
+    b->nf = n_frames;
+    b->interp = interp;
+    for (int w = 0; w < 3; ++w) b->units[w] = (int)units[w];
+    b->lds1 = lds1;
+    b->lds2 = lds2;
+    b->nvx_t = nvx_t;
+    b->wave_f4 = wave_f4;
+    b->waves = waves;
+    b->points = points;
+    b->ws_used = need;
+    b->wg_max[0] = gh::range_batch_max_workgroups(lds1);
+    b->wg_max[1] = gh::doppler_batch_max_workgroups(lds2);
+    b->wg_max[2] = gh::sweep_batch_max_workgroups(interp, nvx_t, waves, (size_t)waves * wave_f4 * 16);
+    for (int w = 0; w < 3; ++w) {
+        if (b->wg_max[w] < 1) {
+            delete b;
+            return fail(GH_EHIP, "occupancy query of the batch kernels failed");
+        }
+        b->wg[w] = b->wg_max[w];
+    }
+    b->d_table = (gh::FrameDesc*)d_ws;
+    b->table.swap(table);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(b->d_table, b->table.data(), b->table.size() * sizeof(gh::FrameDesc),
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "gh_batch_create upload");
+    }
+    *batch = b;
+    return ok();
+}
+
+int gh_batch_tune(gh_batch* batch, int32_t range_workgroups, int32_t doppler_workgroups, int32_t sweep_workgroups,
+                  int32_t sweep_waves) {
+    if (!batch) return fail(GH_EINVAL, "batch is NULL");
+    const int req[3] = {range_workgroups, doppler_workgroups, sweep_workgroups};
+    for (int w = 0; w < 3; ++w)
+        if (req[w] < 0) return fail(GH_EINVAL, "workgroup counts must be >= 0");
+    int rc;
+    if (sweep_waves != 0 && (rc = check_waves(sweep_waves, batch->wave_f4))) return rc;
+    if (sweep_waves != 0 && sweep_waves != batch->waves) {
+        const int mx = gh::sweep_batch_max_workgroups(batch->interp, batch->nvx_t, sweep_waves,
+                                                      (size_t)sweep_waves * batch->wave_f4 * 16);
+        if (mx < 1) return fail(GH_EHIP, "occupancy query of the sweep failed");
+        batch->waves = sweep_waves;
+        batch->wg_max[2] = mx;
+        if (sweep_workgroups == 0) batch->wg[2] = mx;
+    }
+    for (int w = 0; w < 3; ++w)
+        if (req[w] > 0) batch->wg[w] = req[w];
+    return ok();
+}
+
+int gh_batch_get_info(const gh_batch* batch, gh_batch_info* info) {
+    if (!batch || !info) return fail(GH_EINVAL, "batch and info must be non-NULL");
+    memset(info, 0, sizeof(*info));
+    info->n_frames = batch->nf;
+    info->interp = batch->interp;
+    for (int w = 0; w < 3; ++w) {
+        info->units[w] = batch->units[w];
+        info->workgroups[w] = batch->wg[w];
+        info->max_workgroups[w] = batch->wg_max[w];
+    }
+    info->sweep_waves = batch->waves;
+    info->column_height = batch->nvx_t;
+    info->points = batch->points;
+    info->workspace_bytes = (int64_t)batch->ws_used;
+    return ok();
+}
+
+int gh_batch_run(const gh_batch* batch, gh_peak* d_argmax, void* stream) {
+    if (!batch) return fail(GH_EINVAL, "batch is NULL");
+    int dev = -1;
+    int rc = check_aligned({d_argmax});
+    if (rc || (rc = current_device(dev))) return rc;
+    if (dev != batch->device) return fail(GH_EINVAL, "batch created on device %d, current device %d", batch->device, dev);
+    hipStream_t st = (hipStream_t)stream;
+    const gh::FrameDesc* t = batch->d_table;
+    hipError_t e = gh::launch_rd_maps_batch(t, batch->nf, batch->units[0], batch->units[1], batch->lds1, batch->lds2,
+                                            batch->wg[0], batch->wg[1], st);
+    if (e == hipSuccess)
+        e = gh::launch_sweep_batch(t, batch->nf, batch->units[2], batch->interp, batch->nvx_t, batch->wave_f4,
+                                   batch->waves, batch->wg[2], st);
+    if (e == hipSuccess && d_argmax) e = gh::launch_peak_batch(t, batch->nf, d_argmax, st);
+    if (e != hipSuccess) return hip_fail(e, "gh_batch_run launch");
+    return ok();
+}
+
+int gh_batch_frame_maps(const gh_batch* batch, int32_t frame, void** d_maps) {
+    if (!batch || !d_maps) return fail(GH_EINVAL, "batch and d_maps must be non-NULL");
+    if (frame < 0 || frame >= batch->nf) return fail(GH_EINVAL, "frame %d outside [0, %d)", frame, batch->nf);
+    *d_maps = batch->table[frame].maps;
+    return ok();
+}
+
+void gh_batch_destroy(gh_batch* batch) { delete batch; }
 
 }  // extern "C"

@@ -40,6 +40,16 @@ struct GridP {
 
 // ---- small device helpers -------------------------------------------------
 
+// A pointer read from memory (a descriptor table) carries no address space, so
+// its accesses compile to flat instructions; this marks it as global memory
+// (all device arrays of the library are) so they compile to global ones.
+// (Through an integer: a direct cast pair is folded away before address
+// spaces are inferred.)
+template <typename T>
+__device__ __forceinline__ T* as_global(T* p) {
+    return (T*)(__attribute__((address_space(1))) T*)(uintptr_t)p;
+}
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -176,6 +186,55 @@ __device__ __forceinline__ void slab_epilogue(const float (&acc)[NPTS], int nv, 
     }
 }
 
+// Largest of n block maxima (ties to the lowest index), reduced by a whole
+// workgroup of up to 1024 threads; the result is valid in thread 0.  red_v and
+// red_i are LDS arrays of blockDim.x / 64 entries.
+__device__ __forceinline__ void reduce_block_peaks(const gh_peak* __restrict__ blk, int n, float& bv, long long& bi,
+                                                   float* red_v, long long* red_i) {
+    bv = -INFINITY;
+    bi = 0x7fffffffffffffffLL;
+    // sixteen independent loads in flight per thread, then their comparisons
+    for (int b0 = threadIdx.x; b0 < n; b0 += 16 * blockDim.x) {
+        gh_peak p[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int b = b0 + k * (int)blockDim.x;
+            if (b < n) p[k] = blk[b];
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int b = b0 + k * (int)blockDim.x;
+            if (b < n && (p[k].value > bv || (p[k].value == bv && p[k].index < bi))) {
+                bv = p[k].value;
+                bi = p[k].index;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const float v2 = __shfl_xor(bv, off, 64);
+        const long long i2 = __shfl_xor(bi, off, 64);
+        if (v2 > bv || (v2 == bv && i2 < bi)) {
+            bv = v2;
+            bi = i2;
+        }
+    }
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red_v[wid] = bv;
+        red_i[wid] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+            if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bi)) {
+                bv = red_v[w];
+                bi = red_i[w];
+            }
+        }
+    }
+}
+
 // Exclusion list entries that fall in this location's slab (thread 0 only).
 __device__ __forceinline__ int local_exclusions(const int64_t* excl, int nexcl, int loc, int nv, int* out) {
     int n = 0;
@@ -187,9 +246,48 @@ __device__ __forceinline__ int local_exclusions(const int64_t* excl, int nexcl, 
     return n;
 }
 
+// ---- batches of frames --------------------------------------------------------
+// One frame of a batch, in a device-resident table.  The persistent batch
+// kernels walk a global sequence of work units in which each frame's units are
+// contiguous: range units (q, p, chirp group), Doppler units (q, row group),
+// sweep units (one location each, one wave per unit).
+struct FrameDesc {
+    Geom g;
+    GridP gp;
+    const float2* y;     // complex64 [K][Mc][Ms]
+    char* maps;          // complex64 [K][N_r][N_d] (batch workspace)
+    float* dec;          // decision volume or NULL
+    gh_peak* block;      // [Nx*Ny] block maxima
+    int unit0[3];        // first unit of the frame: range, Doppler, sweep
+    int nunit[3];        // units of the frame
+    int nch, nrow, pre_lds;   // map pass shapes (rd_maps_plan)
+    int nvy, parts, chunk;    // sweep columns: lane = part * nvy + ivy, part < parts owns vx rows [part*chunk, +chunk)
+};
+
 // ---- host launchers (return hipError_t of the launches) --------------------
 
 hipError_t launch_rd_maps(const Geom& g, const float2* y, void* maps, int map_dtype, hipStream_t st);
+
+// Work decomposition of the map passes: nch chirps per range workgroup (LDS
+// lds1), nrow range rows per Doppler workgroup (LDS lds2, pre-twiddles in LDS
+// when pre_lds).
+void rd_maps_plan(const Geom& g, int& nch, size_t& lds1, int& nrow, int& pre_lds, size_t& lds2);
+
+// Batch launches (frames: device table of nf descriptors).  Workgroup counts
+// are the persistent grid sizes; each launch clamps them to its unit count.
+hipError_t launch_rd_maps_batch(const FrameDesc* frames, int nf, int range_units, int doppler_units, size_t lds1,
+                                size_t lds2, int wg_range, int wg_doppler, hipStream_t st);
+// Sweep: `waves` waves per workgroup, each with a private LDS slice of
+// wave_f4 float4 (FastGeo records of up to GH_MAX_RX receivers, then the
+// Doppler table of the largest N_d); nvx_t is the compile-time column height.
+int sweep_batch_slice_f4(int interp, int nd_max);
+bool sweep_batch_nvx(int chunk_max, int& nvx_t);
+int sweep_batch_max_workgroups(int interp, int nvx_t, int waves, size_t lds);
+hipError_t launch_sweep_batch(const FrameDesc* frames, int nf, int units, int interp, int nvx_t, int wave_f4,
+                              int waves, int workgroups, hipStream_t st);
+hipError_t launch_peak_batch(const FrameDesc* frames, int nf, gh_peak* argmax, hipStream_t st);
+int range_batch_max_workgroups(size_t lds);
+int doppler_batch_max_workgroups(size_t lds);
 
 hipError_t launch_gh_sweep(const Geom& g, const GridP& gp, const void* maps, int map_dtype, int interp, float* dec,
                            gh_peak* block, const int64_t* excl, int nexcl, hipStream_t st);

@@ -127,20 +127,16 @@ __device__ void lds_fft(float2* buf, int nseq, int stride, int log2m, const floa
     }
 }
 
-// Pass 1: range sub-transform p of `nch` chirps of receiver q.  Map rows are
-// `row_bytes` apart (N_d times the storage size); the spectra are parked as
-// complex64 in the first Mc * 8 bytes of each row.
-__global__ __launch_bounds__(kThreads) void range_pass(Geom g, int nch, size_t row_bytes, const float2* __restrict__ y,
-                                                      char* __restrict__ maps) {
-    extern __shared__ float2 lds[];
+// Pass 1 unit: range sub-transform p of chirps [m0, m0 + nch) of receiver q.
+// Map rows are `row_bytes` apart (N_d times the storage size); the spectra are
+// parked as complex64 in the first Mc * 8 bytes of each row.
+__device__ __forceinline__ void range_unit(const Geom& g, int nch, size_t row_bytes, const float2* __restrict__ y,
+                           char* __restrict__ maps, int m0, int p, int q, float2* lds) {
     const int ms = g.ms, stride = ms + 1;
     float2* buf = lds;                        // [nch][ms + 1]
     float2* pre = buf + nch * stride;         // [ms]
     float2* tw = pre + ms;                    // [ms]
     float2* cen = tw + ms;                    // [ms]
-    const int m0 = blockIdx.x * nch;
-    const int p = blockIdx.y;
-    const int q = blockIdx.z;
     // the inputs are loaded first so that the table build hides their latency
     const float2* yq = y + ((size_t)q * g.mc + m0) * ms;
     float2 x[kBuf / kThreads];
@@ -171,21 +167,25 @@ __global__ __launch_bounds__(kThreads) void range_pass(Geom g, int nch, size_t r
     }
 }
 
-// Pass 2: Doppler transforms of `nrow` range rows of receiver q, in place, and
-// the conversion to the storage type DT (half formats: times 1 / (Ms Mc)).
-// With `pre_lds` false (the largest maps) the pre-twiddles are evaluated inline
-// instead of from an LDS table.
-template <int DT>
-__global__ __launch_bounds__(kThreads) void doppler_pass(Geom g, int nrow, int pre_lds, char* __restrict__ maps) {
+__global__ __launch_bounds__(kThreads) void range_pass(Geom g, int nch, size_t row_bytes, const float2* __restrict__ y,
+                                                      char* __restrict__ maps) {
     extern __shared__ float2 lds[];
+    range_unit(g, nch, row_bytes, y, maps, blockIdx.x * nch, blockIdx.y, blockIdx.z, lds);
+}
+
+// Pass 2 unit: Doppler transforms of range rows [i0, i0 + nrow) of receiver q,
+// in place, and the conversion to the storage type DT (half formats: times
+// 1 / (Ms Mc)).  With `pre_lds` false (the largest maps) the pre-twiddles are
+// evaluated inline instead of from an LDS table.
+template <int DT>
+__device__ __forceinline__ void doppler_unit(const Geom& g, int nrow, int pre_lds, char* __restrict__ maps, int i0, int q,
+                             float2* lds) {
     const int mc = g.mc, pd = g.pd, nd = g.nd, stride = mc + 1;
     const int log2pd = __ffs(pd) - 1;
     float2* buf = lds;                        // [nrow][pd][mc + 1]
     float2* tw = buf + nrow * pd * stride;    // [mc]
     float2* cen = tw + mc;                    // [mc]
     float2* pre = cen + mc;                   // [pd][mc] (pre_lds)
-    const int q = blockIdx.y;
-    const int i0 = blockIdx.x * nrow;
     constexpr int kEs = map_elem_bytes(DT);
     const size_t row_bytes = (size_t)nd * kEs;
     char* rowb = maps + ((size_t)q * g.nr + i0) * row_bytes;
@@ -228,25 +228,127 @@ __global__ __launch_bounds__(kThreads) void doppler_pass(Geom g, int nrow, int p
     }
 }
 
+template <int DT>
+__global__ __launch_bounds__(kThreads) void doppler_pass(Geom g, int nrow, int pre_lds, char* __restrict__ maps) {
+    extern __shared__ float2 lds[];
+    doppler_unit<DT>(g, nrow, pre_lds, maps, blockIdx.x * nrow, blockIdx.y, lds);
+}
+
+// ---- batches: persistent launches over the work units of many frames ----------
+// A workgroup walks units u = blockIdx.x, blockIdx.x + gridDim.x, ... in
+// increasing order, so its frame index only moves forward; it keeps the
+// current frame's descriptor in LDS and reloads it when the frame changes.
+
+// Advance f to the frame holding unit u (all threads agree; unit u exists).
+__device__ __forceinline__ int advance_frame(const FrameDesc* __restrict__ frames, int nf, int f, int u, int which) {
+    while (f + 1 < nf && frames[f + 1].unit0[which] <= u) ++f;
+    return f;
+}
+
+// Copy one frame descriptor into LDS (all threads; bracketed by barriers).
+__device__ __forceinline__ void load_frame(const FrameDesc* src, FrameDesc* dst) {
+    static_assert(sizeof(FrameDesc) % 4 == 0, "descriptor copied as 32-bit words");
+    __syncthreads();
+    const int* s = reinterpret_cast<const int*>(src);
+    int* d = reinterpret_cast<int*>(dst);
+    for (int i = threadIdx.x; i < (int)(sizeof(FrameDesc) / 4); i += blockDim.x) d[i] = s[i];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kThreads) void range_batch(const FrameDesc* __restrict__ frames, int nf, int total) {
+    extern __shared__ float2 lds[];
+    __shared__ FrameDesc fd;
+    int f = 0, loaded = -1;
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        f = advance_frame(frames, nf, f, u, 0);
+        if (f != loaded) {
+            load_frame(frames + f, &fd);
+            loaded = f;
+        }
+        const int lu = u - fd.unit0[0];
+        if (lu >= fd.nunit[0]) continue;   // not reached for a consistent table
+        const int groups = fd.g.mc / fd.nch;
+        const int q = lu / (fd.g.pr * groups), rem = lu - q * fd.g.pr * groups;
+        const int p = rem / groups, grp = rem - p * groups;
+        range_unit(fd.g, fd.nch, (size_t)fd.g.nd * 8, as_global(fd.y), as_global(fd.maps), grp * fd.nch, p, q, lds);
+        __syncthreads();   // the next unit reuses the LDS buffers
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void doppler_batch(const FrameDesc* __restrict__ frames, int nf, int total) {
+    extern __shared__ float2 lds[];
+    __shared__ FrameDesc fd;
+    int f = 0, loaded = -1;
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        f = advance_frame(frames, nf, f, u, 1);
+        if (f != loaded) {
+            load_frame(frames + f, &fd);
+            loaded = f;
+        }
+        const int lu = u - fd.unit0[1];
+        if (lu >= fd.nunit[1]) continue;
+        const int groups = fd.g.nr / fd.nrow;
+        const int q = lu / groups, grp = lu - q * groups;
+        doppler_unit<GH_MAP_C64>(fd.g, fd.nrow, fd.pre_lds, as_global(fd.maps), grp * fd.nrow, q, lds);
+        __syncthreads();
+    }
+}
+
 }  // namespace
+
+// Work decomposition of the two passes (shared by single frames and batches).
+void rd_maps_plan(const Geom& g, int& nch, size_t& lds1, int& nrow, int& pre_lds, size_t& lds2) {
+    // range pass: chirps per workgroup, halved (down to 8) until there are >= 512 workgroups
+    nch = kBuf / g.ms;
+    if (nch > g.mc) nch = g.mc;
+    while (nch > 8 && (long)(g.mc / nch) * g.pr * g.k < 512) nch >>= 1;
+    lds1 = ((size_t)nch * (g.ms + 1) + 3 * (size_t)g.ms) * sizeof(float2);
+    nrow = kBuf / g.nd;
+    if (nrow < 1) nrow = 1;
+    if (nrow > g.nr) nrow = g.nr;
+    lds2 = ((size_t)nrow * g.pd * (g.mc + 1) + 2 * (size_t)g.mc) * sizeof(float2);
+    pre_lds = lds2 + (size_t)g.nd * sizeof(float2) <= 65536 ? 1 : 0;
+    if (pre_lds) lds2 += (size_t)g.nd * sizeof(float2);
+}
+
+int range_batch_max_workgroups(size_t lds) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, range_batch, kThreads, lds) != hipSuccess) return 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+int doppler_batch_max_workgroups(size_t lds) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, doppler_batch, kThreads, lds) != hipSuccess) return 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+hipError_t launch_rd_maps_batch(const FrameDesc* frames, int nf, int range_units, int doppler_units, size_t lds1,
+                                size_t lds2, int wg_range, int wg_doppler, hipStream_t st) {
+    const int w1 = wg_range < range_units ? wg_range : range_units;
+    hipLaunchKernelGGL(range_batch, dim3(w1), dim3(kThreads), lds1, st, frames, nf, range_units);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int w2 = wg_doppler < doppler_units ? wg_doppler : doppler_units;
+    hipLaunchKernelGGL(doppler_batch, dim3(w2), dim3(kThreads), lds2, st, frames, nf, doppler_units);
+    return hipGetLastError();
+}
 
 hipError_t launch_rd_maps(const Geom& g, const float2* y, void* maps_v, int map_dtype, hipStream_t st) {
     char* maps = static_cast<char*>(maps_v);
     const size_t row_bytes = (size_t)g.nd * map_elem_bytes(map_dtype);
-    // range pass: chirps per workgroup, halved (down to 8) until there are >= 512 workgroups
-    int nch = kBuf / g.ms;
-    if (nch > g.mc) nch = g.mc;
-    while (nch > 8 && (long)(g.mc / nch) * g.pr * g.k < 512) nch >>= 1;
-    const size_t lds1 = ((size_t)nch * (g.ms + 1) + 3 * (size_t)g.ms) * sizeof(float2);
+    int nch, nrow, pre_lds;
+    size_t lds1, lds2;
+    rd_maps_plan(g, nch, lds1, nrow, pre_lds, lds2);
     hipLaunchKernelGGL(range_pass, dim3(g.mc / nch, g.pr, g.k), dim3(kThreads), lds1, st, g, nch, row_bytes, y, maps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    int nrow = kBuf / g.nd;
-    if (nrow < 1) nrow = 1;
-    if (nrow > g.nr) nrow = g.nr;
-    size_t lds2 = ((size_t)nrow * g.pd * (g.mc + 1) + 2 * (size_t)g.mc) * sizeof(float2);
-    const int pre_lds = lds2 + (size_t)g.nd * sizeof(float2) <= 65536 ? 1 : 0;
-    if (pre_lds) lds2 += (size_t)g.nd * sizeof(float2);
     const dim3 grid2(g.nr / nrow, g.k);
     if (map_dtype == GH_MAP_F16)
         hipLaunchKernelGGL(doppler_pass<GH_MAP_F16>, grid2, dim3(kThreads), lds2, st, g, nrow, pre_lds, maps);

@@ -177,47 +177,10 @@ __global__ __launch_bounds__(1024) void peak_final_kernel(const gh_peak* __restr
                                                          gh_peak* __restrict__ out, int64_t* __restrict__ slot) {
     __shared__ float red_v[16];
     __shared__ long long red_i[16];
-    float bv = -INFINITY;
-    long long bi = 0x7fffffffffffffffLL;
-    // sixteen independent loads in flight per thread, then their comparisons
-    for (int b0 = threadIdx.x; b0 < n; b0 += 16 * blockDim.x) {
-        gh_peak p[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int b = b0 + k * (int)blockDim.x;
-            if (b < n) p[k] = blk[b];
-        }
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int b = b0 + k * (int)blockDim.x;
-            if (b < n && (p[k].value > bv || (p[k].value == bv && p[k].index < bi))) {
-                bv = p[k].value;
-                bi = p[k].index;
-            }
-        }
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const float v2 = __shfl_xor(bv, off, 64);
-        const long long i2 = __shfl_xor(bi, off, 64);
-        if (v2 > bv || (v2 == bv && i2 < bi)) {
-            bv = v2;
-            bi = i2;
-        }
-    }
-    const int wid = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        red_v[wid] = bv;
-        red_i[wid] = bi;
-    }
-    __syncthreads();
+    float bv;
+    long long bi;
+    reduce_block_peaks(blk, n, bv, bi, red_v, red_i);
     if (threadIdx.x == 0) {
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
-            if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bi)) {
-                bv = red_v[w];
-                bi = red_i[w];
-            }
-        }
         if (out) {
             gh_peak p;
             p.value = bv;

@@ -25,7 +25,9 @@ MAX_SUPPORT = 32
 
 EXPORTS = ("gh_abi_version", "gh_last_error", "gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_workspace_bytes",
            "gh_direct_decision", "gh_bomp_workspace_bytes", "gh_bomp_step", "gh_refine_workspace_bytes",
-           "gh_refine", "gh_direct_points_workspace_bytes", "gh_direct_points", "gh_gh_points")
+           "gh_refine", "gh_direct_points_workspace_bytes", "gh_direct_points", "gh_gh_points",
+           "gh_batch_workspace_bytes", "gh_batch_create", "gh_batch_tune", "gh_batch_get_info", "gh_batch_run",
+           "gh_batch_frame_maps", "gh_batch_destroy")
 
 
 class GhRadar(ctypes.Structure):
@@ -41,6 +43,18 @@ class GhGrid(ctypes.Structure):
 
 class GhPeak(ctypes.Structure):
     _fields_ = [("value", ctypes.c_float), ("reserved", ctypes.c_int32), ("index", ctypes.c_int64)]
+
+
+class GhFrame(ctypes.Structure):
+    _fields_ = [("radar", GhRadar), ("grid", GhGrid), ("d_y", ctypes.c_void_p), ("d_decision", ctypes.c_void_p),
+                ("d_block", ctypes.c_void_p)]
+
+
+class GhBatchInfo(ctypes.Structure):
+    _fields_ = [("n_frames", ctypes.c_int32), ("interp", ctypes.c_int32), ("units", ctypes.c_int32 * 3),
+                ("workgroups", ctypes.c_int32 * 3), ("max_workgroups", ctypes.c_int32 * 3),
+                ("sweep_waves", ctypes.c_int32), ("column_height", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("points", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
 
 
 class GridHopError(RuntimeError):
@@ -80,8 +94,19 @@ def load():
     lib.gh_direct_points_workspace_bytes.restype = sz
     lib.gh_direct_points.argtypes = [rp, vp, vp, i32, vp, vp, vp, vp, sz, vp]
     lib.gh_gh_points.argtypes = [rp, vp, i32, i32, vp, i32, vp, vp, vp, vp]
+    fp = ctypes.POINTER(GhFrame)
+    lib.gh_batch_workspace_bytes.argtypes = [fp, i32]
+    lib.gh_batch_workspace_bytes.restype = sz
+    lib.gh_batch_create.argtypes = [fp, i32, i32, vp, sz, ctypes.POINTER(ctypes.c_void_p), vp]
+    lib.gh_batch_tune.argtypes = [vp, i32, i32, i32, i32]
+    lib.gh_batch_get_info.argtypes = [vp, ctypes.POINTER(GhBatchInfo)]
+    lib.gh_batch_run.argtypes = [vp, pp, vp]
+    lib.gh_batch_frame_maps.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_void_p)]
+    lib.gh_batch_destroy.argtypes = [vp]
+    lib.gh_batch_destroy.restype = None
     for name in ("gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_decision", "gh_bomp_step", "gh_refine",
-                 "gh_direct_points", "gh_gh_points"):
+                 "gh_direct_points", "gh_gh_points", "gh_batch_create", "gh_batch_tune", "gh_batch_get_info",
+                 "gh_batch_run", "gh_batch_frame_maps"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -344,3 +369,138 @@ def gh_points(radar: Radar, maps, theta: torch.Tensor, interp=BILINEAR, want_gra
                             _ptr(value), _ptr(grad), _ptr(grad_rx), _stream(stream)))
     return value, grad, grad_rx
 
+
+
+class Batch:
+    """Frames of different shapes decided together (gh_batch_*): maps, grid-hopping
+    decisions (block maxima, optional volumes) and per-frame argmax, each step one
+    persistent launch over all frames.  Owns the workspace, the output buffers and
+    the C object; the frame tensors `ys` must stay allocated (they are kept here)."""
+
+    def __init__(self, radars, grids, ys, interp=BILINEAR, write_volume=False, stream=None):
+        lib = load()
+        if not (len(radars) == len(grids) == len(ys)) or len(ys) == 0:
+            raise ValueError("radars, grids and ys must be non-empty and of equal length")
+        self.radars, self.grids = list(radars), list(grids)
+        self.ys = [_c64(y) for y in ys]
+        dev = self.ys[0].device
+        self.nf = len(ys)
+        self.interp = int(interp)
+        self.blocks = [peaks_tensor(g.n[0] * g.n[1], dev) for g in self.grids]
+        self.decs = [torch.empty(tuple(g.n), dtype=torch.float32, device=dev) if write_volume else None
+                     for g in self.grids]
+        frames = (GhFrame * self.nf)()
+        for f in range(self.nf):
+            frames[f] = GhFrame(self.radars[f].c_struct, self.grids[f], _ptr(self.ys[f]), _ptr(self.decs[f]),
+                                _ptr(self.blocks[f]))
+        nb = lib.gh_batch_workspace_bytes(frames, self.nf)
+        if nb == 0:
+            raise GridHopError(GH_EINVAL, last_error())
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        self.argmax = peaks_tensor(self.nf, dev)
+        h = ctypes.c_void_p()
+        _check(lib.gh_batch_create(frames, self.nf, self.interp, _ptr(self.ws), nb, ctypes.byref(h),
+                                   _stream(stream)))
+        self._h = h
+
+    @classmethod
+    def from_scenes(cls, scenes, interp=BILINEAR, write_volume=False, device="cuda:0"):
+        radars = [Radar.from_scene(s) for s in scenes]
+        grids = [grid_of(s.grid) for s in scenes]
+        ys = [torch.from_numpy(s.y).to(device) for s in scenes]
+        return cls(radars, grids, ys, interp, write_volume)
+
+    def info(self) -> dict:
+        inf = GhBatchInfo()
+        _check(load().gh_batch_get_info(self._h, ctypes.byref(inf)))
+        return dict(n_frames=inf.n_frames, interp=inf.interp, units=list(inf.units),
+                    workgroups=list(inf.workgroups), max_workgroups=list(inf.max_workgroups),
+                    sweep_waves=inf.sweep_waves, column_height=inf.column_height, points=inf.points,
+                    workspace_bytes=inf.workspace_bytes)
+
+    def tune(self, range_wg=0, doppler_wg=0, sweep_wg=0, sweep_waves=0):
+        _check(load().gh_batch_tune(self._h, int(range_wg), int(doppler_wg), int(sweep_wg), int(sweep_waves)))
+
+    def run(self, want_argmax=True, stream=None) -> torch.Tensor:
+        _check(load().gh_batch_run(self._h, _ptr(self.argmax) if want_argmax else None, _stream(stream)))
+        return self.argmax
+
+    def maps(self, f: int) -> torch.Tensor:
+        """Frame f's complex64 maps [K, N_r, N_d] (a view of the workspace)."""
+        p = ctypes.c_void_p()
+        _check(load().gh_batch_frame_maps(self._h, int(f), ctypes.byref(p)))
+        r = self.radars[f]
+        off = p.value - self.ws.data_ptr()
+        n = r.k * r.nr * r.nd * 8
+        return self.ws[off:off + n].view(torch.complex64).view(r.k, r.nr, r.nd)
+
+    def capture(self, want_argmax=True) -> "torch.cuda.CUDAGraph":
+        """A HIP graph of one run (kernel launches only), after one eager warm-up run."""
+        self.run(want_argmax)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run(want_argmax)
+        return g
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().gh_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(batch: Batch, reps=3, factors=(0.25, 0.5, 1.0, 2.0)) -> dict:
+    """Coordinate search of the batch's persistent launch shapes: sweep waves per
+    workgroup and sweep workgroups (as factors of the resident maximum), then the
+    range and Doppler workgroups, each timed over `reps` runs with HIP events on
+    the current stream.  Leaves the fastest setting applied; returns it with
+    every trial ({"best": {...}, "ms": float, "trials": [...]})."""
+    def timed():
+        batch.run()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(reps):
+            batch.run()
+        end.record()
+        end.synchronize()
+        return start.elapsed_time(end) / reps
+
+    trials = []
+    inf = batch.info()
+    best = dict(range_wg=inf["workgroups"][0], doppler_wg=inf["workgroups"][1], sweep_wg=inf["workgroups"][2],
+                sweep_waves=inf["sweep_waves"])
+    best_ms = timed()
+    trials.append(dict(best, ms=best_ms))
+
+    def consider(**kw):
+        nonlocal best, best_ms
+        cand = dict(best, **kw)
+        try:
+            batch.tune(cand["range_wg"], cand["doppler_wg"], cand["sweep_wg"], cand["sweep_waves"])
+        except GridHopError:
+            return
+        ms = timed()
+        trials.append(dict(cand, ms=ms))
+        if ms < best_ms:
+            best, best_ms = cand, ms
+
+    for waves in (1, 2, 4):
+        try:
+            batch.tune(sweep_waves=waves)
+        except GridHopError:
+            continue
+        m = batch.info()["max_workgroups"][2]
+        for fct in factors:
+            consider(sweep_waves=waves, sweep_wg=max(1, int(m * fct)))
+    for w, key in ((0, "range_wg"), (1, "doppler_wg")):
+        m = batch.info()["max_workgroups"][w]
+        for fct in factors:
+            consider(**{key: max(1, int(m * fct))})
+    batch.tune(best["range_wg"], best["doppler_wg"], best["sweep_wg"], best["sweep_waves"])
+    return dict(best=best, ms=best_ms, trials=trials)

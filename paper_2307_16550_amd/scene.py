@@ -25,6 +25,7 @@ B = 250 MHz, one TX, Q receivers):
          (direct method on the stride-2 64x64x16x16 subgrid)
   cfg 3  K=8, Ms=64,  Mc=32,  1 target, SNR 20 dB, grid 256x256x32x32
   cfg 5  K=8, Ms=512, Mc=256, 8 targets, SNR 5 dB, grid 128x128x32x32
+  batch  64 frames of mixed shapes (make_batch)
 All use Tc = 256 us and zero padding x4 on both axes.  The paper's own
 measurement campaign (433 real frames) is private; these synthetic scenes
 stand in for it.
@@ -194,6 +195,42 @@ def make_scene(cfg: int = 1, trial: int = 0, seed: int | None = None, *, snr_db:
     return Scene(f0=F0, bw=BW, tc=TC, ms=spec["ms"], mc=spec["mc"], pad=PAD, tx=tx, rx=rx,
                  y=y.astype(np.complex64), pos=pos, vel=vel, alpha=alpha, snr_db=snr, grid=grid,
                  centered=centered)
+
+
+# Batching workload: per frame K in [3, 8], Ms in {128, 256}, Mc in {64, 128},
+# 1-5 targets, Nx = Ny in {64, 96, 128, 160, 192}, Nvx = Nvy in {16, 24, 32}
+# (SNR 10 dB, the paper-scale scene's).
+BATCH = dict(frames=64, k=(3, 8), ms=(128, 256), mc=(64, 128), targets=(1, 5), nxy=(64, 96, 128, 160, 192),
+             nv=(16, 24, 32), snr_db=10.0)
+
+
+def batch_seed(trial: int = 0) -> int:
+    return 230716550 + 4000 + trial
+
+
+def make_batch(trial: int = 0, frames: int | None = None, seed: int | None = None, **over) -> list:
+    """Scenes of the batching workload.  The frame shapes are drawn first, in
+    frame order, from default_rng(seed): K, Ms, Mc, targets, Nx = Ny, Nvx = Nvy;
+    frame f is then make_scene's draw with seed + 1 + f.  Keyword arguments
+    replace entries of BATCH (tuples are the choices, (lo, hi) for K and
+    targets)."""
+    spec = dict(BATCH)
+    spec.update(over)
+    nf = spec["frames"] if frames is None else frames
+    base = batch_seed(trial) if seed is None else seed
+    rng = np.random.default_rng(base)
+    shapes = []
+    for _ in range(nf):
+        k = int(rng.integers(spec["k"][0], spec["k"][1] + 1))
+        ms = int(rng.choice(spec["ms"]))
+        mc = int(rng.choice(spec["mc"]))
+        nt = int(rng.integers(spec["targets"][0], spec["targets"][1] + 1))
+        nxy = int(rng.choice(spec["nxy"]))
+        nv = int(rng.choice(spec["nv"]))
+        shapes.append((k, ms, mc, nt, nxy, nv))
+    return [make_scene(1, seed=base + 1 + f, k=k, ms=ms, mc=mc, targets=nt, n=(nxy, nxy, nv, nv),
+                       snr_db=spec["snr_db"])
+            for f, (k, ms, mc, nt, nxy, nv) in enumerate(shapes)]
 
 
 def direct_grid(scene: Scene, cfg: int) -> Grid:

@@ -173,3 +173,62 @@ def test_point_decision_argument_checks(lib):
     assert lib.gh_gh_points(*margs, 0, far, 70000, FAKE, None, None, None) == gh.GH_EINVAL
     assert lib.gh_gh_points(*margs, 0, far, 0, FAKE, None, None, None) == gh.GH_OK
     assert lib.gh_gh_points(*margs, 0, ctypes.c_void_p(0x100000008), 4, FAKE, None, None, None) == gh.GH_EINVAL
+
+
+def batch_frames(specs):
+    """gh_frame array from (k, ms, mc, pad_d, grid n) tuples; device pointers are fake."""
+    keep, frames = [], (gh.GhFrame * len(specs))()
+    for f, (k, ms, mc, pad_d, n) in enumerate(specs):
+        s = sc.make_scene(1, 0, k=k, ms=ms, mc=mc, n=n)
+        r = gh.Radar(s.f0, s.bw, s.tc, ms, mc, s.tx, s.rx, 4, pad_d, 1)
+        keep.append(r)
+        frames[f] = gh.GhFrame(r.c_struct, gh.grid_of(s.grid), FAKE, None, FAKE)
+    return frames, keep
+
+
+def test_batch_struct_layout():
+    # gh_frame: gh_radar (4 doubles, 6 int32, tx[2], rx pointer = 80 bytes), gh_grid (80), 3 pointers
+    assert ctypes.sizeof(gh.GhFrame) == 184 and gh.GhFrame.d_y.offset == 160
+    # gh_batch_info: 14 int32, then two int64
+    assert ctypes.sizeof(gh.GhBatchInfo) == 72 and gh.GhBatchInfo.points.offset == 56
+
+
+def test_batch_argument_checks(lib):
+    frames, keep = batch_frames([(3, 64, 32, 4, (8, 8, 4, 4)), (4, 128, 64, 2, (16, 12, 3, 24))])
+    need = lib.gh_batch_workspace_bytes(frames, 2)
+    maps = 3 * 256 * 128 * 8 + 4 * 512 * 128 * 8
+    assert maps < need <= maps + 2 * 1024 + 3 * 256 + 2 * 4096
+    assert lib.gh_batch_workspace_bytes(frames, 0) == 0
+    out = ctypes.c_void_p()
+    big = 1 << 40
+    assert lib.gh_batch_create(frames, 2, 0, FAKE, big, None, None) == gh.GH_EINVAL
+    assert lib.gh_batch_create(frames, 0, 0, FAKE, big, ctypes.byref(out), None) == gh.GH_EINVAL
+    assert lib.gh_batch_create(frames, 2, 2, FAKE, big, ctypes.byref(out), None) == gh.GH_EINVAL
+    assert lib.gh_batch_create(frames, 2, 0, None, big, ctypes.byref(out), None) == gh.GH_EINVAL
+    assert lib.gh_batch_create(frames, 2, 0, FAKE, need - 1, ctypes.byref(out), None) == gh.GH_EWORKSPACE
+    assert out.value is None
+    # invalid frame radar: named by its index
+    bad, keep2 = batch_frames([(3, 64, 32, 4, (8, 8, 4, 4)), (3, 64, 32, 4, (8, 8, 4, 4))])
+    bad[1].radar.n_samples = 48
+    assert lib.gh_batch_workspace_bytes(bad, 2) == 0
+    assert "frame 1" in gh.last_error() and "n_samples" in gh.last_error()
+    # shapes outside the batch sweep
+    for spec in [(3, 64, 8, 1, (8, 8, 4, 4)),        # N_d = 8 < 16
+                 (3, 64, 32, 4, (8, 8, 2, 65)),       # Nvy > 64
+                 (3, 64, 32, 4, (8, 8, 33, 64)),      # 33 vx points per lane
+                 (3, 64, 32, 4, (8, 8, 65, 32))]:     # 33 vx points per lane
+        fr, keep3 = batch_frames([spec])
+        assert lib.gh_batch_create(fr, 1, 0, FAKE, big, ctypes.byref(out), None) == gh.GH_EUNSUPPORTED, spec
+    # NULL and misaligned frame pointers
+    frames[1].d_block = None
+    assert lib.gh_batch_create(frames, 2, 0, FAKE, big, ctypes.byref(out), None) == gh.GH_EINVAL
+    frames[1].d_block = FAKE.value
+    frames[0].d_y = 0x1008
+    assert lib.gh_batch_create(frames, 2, 0, FAKE, big, ctypes.byref(out), None) == gh.GH_EINVAL
+    # NULL batch objects
+    info = gh.GhBatchInfo()
+    assert lib.gh_batch_run(None, None, None) == gh.GH_EINVAL
+    assert lib.gh_batch_tune(None, 0, 0, 0, 0) == gh.GH_EINVAL
+    assert lib.gh_batch_get_info(None, ctypes.byref(info)) == gh.GH_EINVAL
+    assert lib.gh_batch_frame_maps(None, 0, ctypes.byref(out)) == gh.GH_EINVAL
+    lib.gh_batch_destroy(None)
