@@ -18,6 +18,9 @@ Radar", Monnoyer et al.):
   refine.py  off-grid Newton refinement of the direct decision
   grad.py    decisions at continuous points with their gradients with respect
              to (x, y, vx, vy) and the receiver positions
+  factor.py  the factorised location-then-velocity decisions of eqs. (5)-(6),
+             direct and by grid hopping (range spectra with bilinear, Keys or
+             polar range interpolation; nearest-bin Doppler)
 
 Every function is pinned by tests in tests/test_oracle_*.py against closed
 forms, brute force on tiny inputs, invariants, or values the paper prints.
