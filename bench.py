@@ -175,6 +175,33 @@ def cpu_baseline(job):
 
 # ----------------------------------------------------------------------------- GPU benchmark
 
+def factored_timings(gh, torch, radar, grid, y, stream, reps=50):
+    """The paper's factorised estimator (eqs. (5)-(6)) on the step's frame: grid hopping with
+    polar range interpolation and nearest-bin Doppler (range spectra included), and the direct
+    method with FP32 matrix-core range zoom; ms per frame by HIP events."""
+    spec = gh.range_spectra(radar, y)
+    ws_g = torch.empty(gh.factored_workspace_bytes(radar, grid, gh.FACTOR_GH), dtype=torch.uint8, device=y.device)
+    ws_d = torch.empty(gh.factored_workspace_bytes(radar, grid, gh.FACTOR_DIRECT), dtype=torch.uint8,
+                       device=y.device)
+    out = {}
+    for name, fn in (("gh_polar_nearest_ms", lambda: (gh.range_spectra(radar, y, spec),
+                                                      gh.factored_decision(radar, grid, gh.FACTOR_GH, spec, gh.POLAR,
+                                                                           ws=ws_g))),
+                     ("direct_f32_ms", lambda: gh.factored_decision(radar, grid, gh.FACTOR_DIRECT, y, ws=ws_d))):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / reps
+    out["locations"] = grid.n[0] * grid.n[1]
+    out["velocities"] = grid.n[2] * grid.n[3]
+    return out
+
+
 def batch_workload(gh, sc, torch, stream):
     """Frames/s and grid points/s of the batching workload (graph replays, HIP events)."""
     scenes = sc.make_batch()
@@ -354,6 +381,7 @@ def main():
                      "avg_launch_us": t_sweep * 1e6},
     }
 
+    line["factored"] = factored_timings(gh, torch, radar, grid, y, stream)
     if not args.no_batch:
         line["batch"] = batch_workload(gh, sc, torch, stream)
 

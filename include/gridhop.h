@@ -60,7 +60,12 @@ typedef enum {
     GH_EWORKSPACE = -4     /* caller workspace smaller than the matching *_workspace_bytes() */
 } gh_status;
 
-typedef enum { GH_INTERP_BILINEAR = 0, GH_INTERP_BICUBIC = 1 } gh_interp;
+/* Interpolation rules.  GH_INTERP_POLAR (the paper's range rule, Sec. IV) is
+ * accepted by gh_factored_decision only. */
+typedef enum { GH_INTERP_BILINEAR = 0, GH_INTERP_BICUBIC = 1, GH_INTERP_POLAR = 2 } gh_interp;
+
+/* Method of gh_factored_decision. */
+typedef enum { GH_FACTOR_DIRECT = 0, GH_FACTOR_GRID_HOPPING = 1 } gh_factor_method;
 
 /* Storage of range-Doppler maps.  GH_MAP_C64: complex64, the map itself.
  * GH_MAP_F16 / GH_MAP_BF16: (re, im) pairs of IEEE binary16 / bfloat16
@@ -238,6 +243,49 @@ int gh_direct_points(const gh_radar *radar, const void *d_y, const double *d_the
 int gh_gh_points(const gh_radar *radar, const void *d_maps, int32_t map_dtype, int32_t interp,
                  const double *d_theta, int32_t n_points, double *d_value, double *d_grad, double *d_grad_rx,
                  void *stream);
+
+/* ---- Factorised decisions (paper Sec. III, eqs. (5)-(6), and Sec. IV) ------
+ * The paper's own sequence: the location first, from the energy of the
+ * per-chirp range correlations,
+ *   E(x) = sum_q sum_m |<Y_q[m], a(f_r,q(x))>|^2,           x^ = argmax over the location grid,
+ * then the velocity at x^ from each receiver's chirp sequence of range
+ * correlations there, g_q[m],
+ *   V(v) = sum_q |<g_q, b(f_d,q(x^, v))>|^2,                 v^ = argmax over the velocity grid
+ * (the atom of eq. (6) read as the Doppler atom b).  Grid hopping replaces the
+ * scalar products of (5) by a range interpolation of per-chirp range spectra
+ * (gh_range_spectra) and those of (6) by the nearest bin, round(t_d), of the
+ * zero-padded FFT over chirps of the interpolated g_q (Sec. IV: a single
+ * index in Doppler). */
+
+/* Per-chirp zero-padded range spectra (the range FFT of Sec. IV, before any
+ * transform over chirps): spectra[q][i][m] = sum_s Y_q[m][s]
+ * exp(-j 2 pi i (s - c_s) / N_r), c_s as in gh_rd_maps.  d_y: complex64
+ * [K][Mc][Ms]; d_spectra: complex64 [K][N_r][Mc] (written; must not overlap
+ * d_y).  FP32. */
+int gh_range_spectra(const gh_radar *radar, const void *d_y, void *d_spectra, void *stream);
+
+/* Workspace of gh_factored_decision in bytes (0 on invalid arguments). */
+size_t gh_factored_workspace_bytes(const gh_radar *radar, const gh_grid *grid, int32_t method);
+
+/* Factorised decision, eqs. (5)-(6).
+ * method GH_FACTOR_DIRECT: d_input = the frames (complex64 [K][Mc][Ms]); the
+ *   correlations of (5) by the range zoom of gh_direct_decision (gemm_dtype
+ *   F32 or BF16 operands), those of (6) exactly (FP32 per chirp, fixed-point
+ *   phases); range_interp ignored.
+ * method GH_FACTOR_GRID_HOPPING: d_input = gh_range_spectra of the frames;
+ *   range_interp = GH_INTERP_BILINEAR, GH_INTERP_BICUBIC (Keys, a = -1/2) or
+ *   GH_INTERP_POLAR: the three bins around the nearest one, weighted by the
+ *   circle through their three atoms (angle theta per bin from the atoms'
+ *   chord lengths, |f(1) - f(-1)|^2 / |f(1) - f(0)|^2 = 2 (1 + cos theta));
+ *   taps wrap with the centring sign; gemm_dtype ignored.
+ * d_loc: float [Nx][Ny], E(x) (NULL: not written).  d_vel: float [Nvx][Nvy],
+ * V(v) at the selected location (NULL: not written).  d_result: gh_peak [2]:
+ * [0] = (E(x^), location index ix*Ny + iy), [1] = (V(v^), linear 4D grid
+ * index of (x^, v^)); ties to the lowest index.  Everything stays on the
+ * device. */
+int gh_factored_decision(const gh_radar *radar, const gh_grid *grid, int32_t method, int32_t range_interp,
+                         int32_t gemm_dtype, const void *d_input, void *d_ws, size_t ws_bytes, float *d_loc,
+                         float *d_vel, gh_peak *d_result, void *stream);
 
 /* ---- Batches of frames (batching axis; not in the paper) -------------------
  * Many frames of different shapes (radar, grid) decided together: their maps

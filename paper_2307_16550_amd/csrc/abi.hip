@@ -414,6 +414,69 @@ int gh_gh_points(const gh_radar* radar, const void* d_maps, int32_t map_dtype, i
     return ok();
 }
 
+int gh_range_spectra(const gh_radar* radar, const void* d_y, void* d_spectra, void* stream) {
+    gh::Geom g;
+    int rc = make_geom(radar, g);
+    if (rc) return rc;
+    if (!d_y || !d_spectra) return fail(GH_EINVAL, "d_y and d_spectra must be non-NULL");
+    if ((rc = check_aligned({d_y, d_spectra}))) return rc;
+    const size_t ybytes = (size_t)g.k * g.mc * g.ms * 8, sbytes = (size_t)g.k * g.nr * g.mc * 8;
+    const char *y0 = (const char*)d_y, *s0 = (const char*)d_spectra;
+    if (y0 < s0 + sbytes && s0 < y0 + ybytes) return fail(GH_EINVAL, "d_y and d_spectra overlap");
+    if ((rc = check_device())) return rc;
+    hipError_t e = gh::launch_range_spectra(g, (const float2*)d_y, (float2*)d_spectra, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gh_range_spectra launch");
+    return ok();
+}
+
+size_t gh_factored_workspace_bytes(const gh_radar* radar, const gh_grid* grid, int32_t method) {
+    gh::Geom g;
+    gh::GridP gp;
+    if (make_geom(radar, g) || make_grid(grid, gp)) return 0;
+    if (method != GH_FACTOR_DIRECT && method != GH_FACTOR_GRID_HOPPING) {
+        fail(GH_EINVAL, "method must be GH_FACTOR_DIRECT or GH_FACTOR_GRID_HOPPING");
+        return 0;
+    }
+    ok();
+    return gh::factored_ws_bytes(g, gp, method);
+}
+
+int gh_factored_decision(const gh_radar* radar, const gh_grid* grid, int32_t method, int32_t range_interp,
+                         int32_t gemm_dtype, const void* d_input, void* d_ws, size_t ws_bytes, float* d_loc,
+                         float* d_vel, gh_peak* d_result, void* stream) {
+    gh::Geom g;
+    gh::GridP gp;
+    int rc = make_geom(radar, g);
+    if (rc || (rc = make_grid(grid, gp))) return rc;
+    if (method != GH_FACTOR_DIRECT && method != GH_FACTOR_GRID_HOPPING)
+        return fail(GH_EINVAL, "method must be GH_FACTOR_DIRECT or GH_FACTOR_GRID_HOPPING");
+    if (method == GH_FACTOR_DIRECT && (rc = check_gemm(gemm_dtype))) return rc;
+    if (method == GH_FACTOR_GRID_HOPPING && range_interp != GH_INTERP_BILINEAR && range_interp != GH_INTERP_BICUBIC &&
+        range_interp != GH_INTERP_POLAR)
+        return fail(GH_EINVAL, "range_interp must be GH_INTERP_BILINEAR, GH_INTERP_BICUBIC or GH_INTERP_POLAR");
+    if (!d_input || !d_ws || !d_result) return fail(GH_EINVAL, "d_input, d_ws and d_result must be non-NULL");
+    if ((rc = check_aligned({d_input, d_ws, d_loc, d_vel, d_result}))) return rc;
+    const size_t need = gh::factored_ws_bytes(g, gp, method);
+    if (ws_bytes < need) return fail(GH_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    // polar rule: circle angle per bin from the chord lengths of three neighbouring
+    // range atoms, |f(a) - f(b)|^2 = 2 Ms - 2 Re <f(a), f(b)>
+    double theta = 0.0;
+    if (method == GH_FACTOR_GRID_HOPPING && range_interp == GH_INTERP_POLAR) {
+        const double c = g.centered ? (g.ms - 1) / 2.0 : 0.0;
+        double re1 = 0.0, re2 = 0.0;
+        for (int s = 0; s < g.ms; ++s) {
+            re1 += cos(2.0 * M_PI * (s - c) / g.nr);
+            re2 += cos(4.0 * M_PI * (s - c) / g.nr);
+        }
+        theta = acos((g.ms - re2) / (2.0 * (g.ms - re1)) - 1.0);
+    }
+    if ((rc = check_device())) return rc;
+    hipError_t e = gh::launch_factored(g, gp, method, range_interp, theta, gemm_dtype, d_input, d_ws, d_loc, d_vel,
+                                       d_result, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gh_factored_decision launch");
+    return ok();
+}
+
 size_t gh_batch_workspace_bytes(const gh_frame* frames, int32_t n_frames) {
     std::vector<gh::Geom> gs;
     std::vector<gh::GridP> gps;

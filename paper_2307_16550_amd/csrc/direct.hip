@@ -235,6 +235,15 @@ size_t direct_ws_bytes(const Geom& g, const GridP& gp, int /*gemm*/) {
     return (size_t)g.k * gp.nloc * g.mc * sizeof(float2);
 }
 
+hipError_t launch_direct_range(const Geom& g, const GridP& gp, const float2* y, int gemm, float2* G, hipStream_t st) {
+    const dim3 g1((gp.nloc + 16 * kWaves - 1) / (16 * kWaves), (g.mc + 16 * kNT - 1) / (16 * kNT), g.k);
+    if (gemm == GH_GEMM_BF16)
+        hipLaunchKernelGGL(direct_range_zoom<true>, g1, dim3(kThreads), 0, st, g, gp, y, G);
+    else
+        hipLaunchKernelGGL(direct_range_zoom<false>, g1, dim3(kThreads), 0, st, g, gp, y, G);
+    return hipGetLastError();
+}
+
 hipError_t launch_direct(const Geom& g, const GridP& gp, const float2* y, int gemm, void* ws, float* dec,
                          gh_peak* block, const int64_t* excl, int nexcl, hipStream_t st) {
     float2* gws = static_cast<float2*>(ws);

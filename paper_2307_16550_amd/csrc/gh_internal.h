@@ -289,6 +289,17 @@ hipError_t launch_peak_batch(const FrameDesc* frames, int nf, gh_peak* argmax, h
 int range_batch_max_workgroups(size_t lds);
 int doppler_batch_max_workgroups(size_t lds);
 
+// The range pass alone into compact per-chirp spectra, complex64 [K][N_r][Mc].
+hipError_t launch_range_spectra(const Geom& g, const float2* y, float2* spectra, hipStream_t st);
+
+// Factorised decisions (eqs. (5)-(6)): see factor.hip.
+size_t factored_ws_bytes(const Geom& g, const GridP& gp, int method);
+hipError_t launch_factored(const Geom& g, const GridP& gp, int method, int range_interp, double polar_theta,
+                           int gemm, const void* input, void* ws, float* loc, float* vel, gh_peak* result,
+                           hipStream_t st);
+// The range zoom of the direct decision alone: G_q[x][m], float2 [K][Nloc][Mc].
+hipError_t launch_direct_range(const Geom& g, const GridP& gp, const float2* y, int gemm, float2* G, hipStream_t st);
+
 hipError_t launch_gh_sweep(const Geom& g, const GridP& gp, const void* maps, int map_dtype, int interp, float* dec,
                            gh_peak* block, const int64_t* excl, int nexcl, hipStream_t st);
 

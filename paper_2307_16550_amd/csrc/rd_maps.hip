@@ -340,6 +340,15 @@ hipError_t launch_rd_maps_batch(const FrameDesc* frames, int nf, int range_units
     return hipGetLastError();
 }
 
+hipError_t launch_range_spectra(const Geom& g, const float2* y, float2* spectra, hipStream_t st) {
+    int nch, nrow, pre_lds;
+    size_t lds1, lds2;
+    rd_maps_plan(g, nch, lds1, nrow, pre_lds, lds2);
+    hipLaunchKernelGGL(range_pass, dim3(g.mc / nch, g.pr, g.k), dim3(kThreads), lds1, st, g, nch,
+                       (size_t)g.mc * sizeof(float2), y, reinterpret_cast<char*>(spectra));
+    return hipGetLastError();
+}
+
 hipError_t launch_rd_maps(const Geom& g, const float2* y, void* maps_v, int map_dtype, hipStream_t st) {
     char* maps = static_cast<char*>(maps_v);
     const size_t row_bytes = (size_t)g.nd * map_elem_bytes(map_dtype);

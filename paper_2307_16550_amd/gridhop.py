@@ -18,7 +18,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libgridhop.so")
 
 GH_OK, GH_EINVAL, GH_EUNSUPPORTED, GH_EHIP, GH_EWORKSPACE = 0, -1, -2, -3, -4
-BILINEAR, BICUBIC = 0, 1
+BILINEAR, BICUBIC, POLAR = 0, 1, 2
+FACTOR_DIRECT, FACTOR_GH = 0, 1
 GEMM_F32, GEMM_BF16 = 0, 1
 MAP_C64, MAP_F16, MAP_BF16 = 0, 1, 2
 MAX_SUPPORT = 32
@@ -26,6 +27,7 @@ MAX_SUPPORT = 32
 EXPORTS = ("gh_abi_version", "gh_last_error", "gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_workspace_bytes",
            "gh_direct_decision", "gh_bomp_workspace_bytes", "gh_bomp_step", "gh_refine_workspace_bytes",
            "gh_refine", "gh_direct_points_workspace_bytes", "gh_direct_points", "gh_gh_points",
+           "gh_range_spectra", "gh_factored_workspace_bytes", "gh_factored_decision",
            "gh_batch_workspace_bytes", "gh_batch_create", "gh_batch_tune", "gh_batch_get_info", "gh_batch_run",
            "gh_batch_frame_maps", "gh_batch_destroy")
 
@@ -94,6 +96,10 @@ def load():
     lib.gh_direct_points_workspace_bytes.restype = sz
     lib.gh_direct_points.argtypes = [rp, vp, vp, i32, vp, vp, vp, vp, sz, vp]
     lib.gh_gh_points.argtypes = [rp, vp, i32, i32, vp, i32, vp, vp, vp, vp]
+    lib.gh_range_spectra.argtypes = [rp, vp, vp, vp]
+    lib.gh_factored_workspace_bytes.argtypes = [rp, gp_, i32]
+    lib.gh_factored_workspace_bytes.restype = sz
+    lib.gh_factored_decision.argtypes = [rp, gp_, i32, i32, i32, vp, vp, sz, vp, vp, pp, vp]
     fp = ctypes.POINTER(GhFrame)
     lib.gh_batch_workspace_bytes.argtypes = [fp, i32]
     lib.gh_batch_workspace_bytes.restype = sz
@@ -105,7 +111,7 @@ def load():
     lib.gh_batch_destroy.argtypes = [vp]
     lib.gh_batch_destroy.restype = None
     for name in ("gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_decision", "gh_bomp_step", "gh_refine",
-                 "gh_direct_points", "gh_gh_points", "gh_batch_create", "gh_batch_tune", "gh_batch_get_info",
+                 "gh_direct_points", "gh_gh_points", "gh_range_spectra", "gh_factored_decision", "gh_batch_create", "gh_batch_tune", "gh_batch_get_info",
                  "gh_batch_run", "gh_batch_frame_maps"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -369,6 +375,45 @@ def gh_points(radar: Radar, maps, theta: torch.Tensor, interp=BILINEAR, want_gra
                             _ptr(value), _ptr(grad), _ptr(grad_rx), _stream(stream)))
     return value, grad, grad_rx
 
+
+
+def range_spectra(radar: Radar, y: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Per-chirp zero-padded range spectra, complex64 [K, N_r, Mc]."""
+    lib = load()
+    _c64(y)
+    if out is None:
+        out = torch.empty((radar.k, radar.nr, radar.mc), dtype=torch.complex64, device=y.device)
+    _check(lib.gh_range_spectra(ctypes.byref(radar.c_struct), _ptr(y), _ptr(_c64(out)), _stream(stream)))
+    return out
+
+
+def factored_workspace_bytes(radar: Radar, grid: GhGrid, method: int) -> int:
+    n = load().gh_factored_workspace_bytes(ctypes.byref(radar.c_struct), ctypes.byref(grid), int(method))
+    if n == 0:
+        raise GridHopError(GH_EINVAL, last_error())
+    return n
+
+
+def factored_decision(radar: Radar, grid: GhGrid, method: int, inp: torch.Tensor, range_interp=POLAR,
+                      gemm=GEMM_F32, ws=None, loc=None, vel=None, result=None, write_loc=True, write_vel=True,
+                      stream=None):
+    """Eqs. (5)-(6): (E [Nx, Ny] or None, V [Nvx, Nvy] or None, result gh_peak [2]: (E(x^), location),
+    (V(v^), 4D index)).  inp: the frames (FACTOR_DIRECT) or range_spectra (FACTOR_GH)."""
+    lib = load()
+    _c64(inp)
+    dev = inp.device
+    if ws is None:
+        ws = torch.empty(factored_workspace_bytes(radar, grid, method), dtype=torch.uint8, device=dev)
+    if loc is None and write_loc:
+        loc = torch.empty((grid.n[0], grid.n[1]), dtype=torch.float32, device=dev)
+    if vel is None and write_vel:
+        vel = torch.empty((grid.n[2], grid.n[3]), dtype=torch.float32, device=dev)
+    if result is None:
+        result = peaks_tensor(2, dev)
+    _check(lib.gh_factored_decision(ctypes.byref(radar.c_struct), ctypes.byref(grid), int(method), int(range_interp),
+                                    int(gemm), _ptr(inp), _ptr(ws), ws.numel(), _ptr(loc), _ptr(vel), _ptr(result),
+                                    _stream(stream)))
+    return loc, vel, result
 
 
 class Batch:

@@ -232,3 +232,28 @@ def test_batch_argument_checks(lib):
     assert lib.gh_batch_get_info(None, ctypes.byref(info)) == gh.GH_EINVAL
     assert lib.gh_batch_frame_maps(None, 0, ctypes.byref(out)) == gh.GH_EINVAL
     lib.gh_batch_destroy(None)
+
+
+def test_factored_argument_checks(lib):
+    r = radar()
+    far = ctypes.c_void_p(0x100000000)
+    rs = ctypes.byref(r.c_struct)
+    assert lib.gh_range_spectra(rs, None, far, None) == gh.GH_EINVAL
+    assert lib.gh_range_spectra(rs, FAKE, ctypes.c_void_p(0x1008), None) == gh.GH_EINVAL    # misaligned
+    assert lib.gh_range_spectra(rs, FAKE, FAKE, None) == gh.GH_EINVAL                       # overlap
+    g = ctypes.byref(GRID)
+    nd = lib.gh_factored_workspace_bytes(rs, g, gh.FACTOR_DIRECT)
+    ng = lib.gh_factored_workspace_bytes(rs, g, gh.FACTOR_GH)
+    # direct: the range zoom G (K x Nloc x Mc complex64) plus the peak buffers
+    assert nd - ng == 3 * 32 * 32 * 32 * 8 and ng >= 32 * 32 * 16
+    assert lib.gh_factored_workspace_bytes(rs, g, 2) == 0
+    args = [rs, g]
+    assert lib.gh_factored_decision(*args, 2, 0, 0, FAKE, FAKE, nd, None, None, FAKE, None) == gh.GH_EINVAL
+    assert lib.gh_factored_decision(*args, gh.FACTOR_GH, 3, 0, FAKE, FAKE, ng, None, None, FAKE, None) == gh.GH_EINVAL
+    assert lib.gh_factored_decision(*args, gh.FACTOR_DIRECT, 0, 2, FAKE, FAKE, nd, None, None, FAKE, None) == gh.GH_EINVAL
+    assert lib.gh_factored_decision(*args, gh.FACTOR_GH, gh.POLAR, 0, FAKE, FAKE, ng - 1, None, None, FAKE,
+                                    None) == gh.GH_EWORKSPACE
+    assert lib.gh_factored_decision(*args, gh.FACTOR_GH, gh.POLAR, 0, FAKE, FAKE, ng, None, None, None,
+                                    None) == gh.GH_EINVAL
+    # the polar rule is for the factorised decision only
+    assert lib.gh_decision(rs, g, FAKE, 0, gh.POLAR, None, FAKE, None, None) == gh.GH_EINVAL
