@@ -14,7 +14,12 @@ one stream with no host synchronisation inside the step:
      argmax-only sweep with the support excluded, least-squares fit, residual);
   5. Newton refinement of the 3 selected cells.
 Grid points evaluated per step: 4 x 16,777,216 (grid hopping) + 1,048,576
-(direct).  `value` is that count divided by the measured step time.
+(direct).  `value` is that count divided by the measured step time.  The
+step is captured once in a HIP graph (kernel launches and one device copy;
+no memset) and the timed steps are graph replays; the per-row times come
+from eager steps with HIP events, and after the replays the step's outputs
+(argmax cells, Block-OMP support and coefficients, refined estimates) are
+compared with those of an eager step (`graph_matches_eager`).
 
 The roofline object covers the dominant kernel, the grid-hopping sweep of
 step 2, timed with HIP events on the stream it runs on; its algorithmic bytes
@@ -46,9 +51,11 @@ CFG = 2
 HBM_PEAK_GBS = 8000.0
 BOMP_ITERS = 3
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "gh_sweep_columns_paper_scale_hbm_traffic.md")
-SWEEP_SOURCES = [os.path.join(ROOT, "paper_2307_16550_amd", "csrc", f)
-                 for f in ("sweep_fast.hip", "sweep_table.h", "gh_internal.h")]
+SWEEP_SOURCES = [os.path.join(ROOT, "paper_2307_16550_amd", "csrc", f) for f in ("sweep_fast.hip", "sweep_table.h")]
+INTERNAL_HEADER = os.path.join(ROOT, "paper_2307_16550_amd", "csrc", "gh_internal.h")
+DEVICE_PART_END = "// ---- batches of frames"   # gh_internal.h from here on declares host launchers only
 BATCH_REPLAYS = 10
+EAGER_ROW_STEPS = 20
 
 
 def recorded_traffic():
@@ -62,7 +69,9 @@ def recorded_traffic():
         for f in SWEEP_SOURCES:
             with open(f, "rb") as fh:
                 h.update(fh.read())
-    except OSError:
+        header = open(INTERNAL_HEADER).read()
+        h.update(header[:header.index(DEVICE_PART_END)].encode())
+    except (OSError, ValueError):
         return None
     m_bytes = re.search(r"^traffic_bytes_per_launch:\s*(\d+)", text, re.M)
     m_sha = re.search(r"^sweep_source_sha256:\s*([0-9a-f]{64})", text, re.M)
@@ -312,14 +321,29 @@ def main():
             e[5].record(stream)
             marks.append(e)
 
+    # eager steps: warm-up, then per-row HIP events on the launch stream
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(min(args.steps, EAGER_ROW_STEPS)):
         step(True)
     torch.cuda.synchronize()
+    snap = lambda: [t.clone() for t in (arg, darg, bomp.support, bomp.alpha, theta)]
+    ref = snap()
+
+    # the timed steps: the whole step captured once in a HIP graph and replayed
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step(False)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    graph_matches_eager = all(torch.equal(a, b) for a, b in zip(snap(), ref))
 
     def avg(i, j):
         return float(np.mean([m[i].elapsed_time(m[j]) for m in marks])) * 1e-3
@@ -366,6 +390,8 @@ def main():
             "direct_grid": list(dgrid_s.n),
             "interp": args.interp,
         },
+        "step_launch": "hip_graph",
+        "graph_matches_eager": graph_matches_eager,
         "rows_ms": {"rd_maps": t_maps * 1e3, "gh_sweep": t_sweep * 1e3, "argmax": t_arg * 1e3,
                     "direct": t_dir * 1e3, "bomp_refine_rest": (t_total - t_maps - t_sweep - t_arg - t_dir) * 1e3},
         "gh_points_per_s": n_gh / (t_maps + t_sweep + t_arg),
