@@ -203,11 +203,11 @@ __device__ __forceinline__ void table_build(float4* tabl, const char* mq, const 
 // Accumulate |I|^2 of one receiver at the points t, t + ax, ... of a column
 // (NVX points, evaluated in batches of LDS reads; batches starting at or
 // beyond `jlim` are skipped, a wave-uniform bound).
-template <int INTERP, int NVX>
+template <int INTERP, int NVX, int WANT = (INTERP ? 4 : 8)>
 __device__ __forceinline__ void eval_column(float (&acc)[NVX], const float4* tab, uint32_t t, uint32_t ax,
                                             uint32_t bin_lo, uint32_t log2nd, uint32_t fsh, int jlim) {
     constexpr int kEntry = INTERP ? 2 : 1;
-    constexpr int kWant = INTERP ? 4 : 8;          // LDS reads kept in flight per column
+    constexpr int kWant = WANT;                    // LDS reads kept in flight per column
     constexpr int kBatch = NVX < kWant ? NVX : kWant;
 #pragma unroll
     for (int j0 = 0; j0 < NVX; j0 += kBatch) {
