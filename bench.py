@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batching-workload measurement")
+    ap.add_argument("--step-only", action="store_true",
+                    help="time the step alone: no side measurements, batch or CPU baseline (profiling)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only measure the batching workload and print its JSON object (profiling)")
     ap.add_argument("--interp", choices=["bilinear", "bicubic"], default="bilinear")
@@ -350,19 +352,69 @@ def main():
 
     t_maps, t_sweep, t_arg, t_dir, t_total = avg(0, 1), avg(1, 2), avg(2, 3), avg(3, 4), avg(0, 5)
 
-    # the direct decision with BF16 matrix-core operands, timed on its own (not part of the step)
-    ws_b = torch.empty(gh.direct_workspace_bytes(radar, dgrid, gh.GEMM_BF16), dtype=torch.uint8, device=dev)
-    ddec_b = torch.empty_like(ddec)
-    for _ in range(3):
-        gh.direct_decision(radar, dgrid, y, gemm=gh.GEMM_BF16, ws=ws_b, dec=ddec_b, block=dblock, want_argmax=False)
-    eb0, eb1 = ev(), ev()
-    eb0.record(stream)
-    for _ in range(10):
-        gh.direct_decision(radar, dgrid, y, gemm=gh.GEMM_BF16, ws=ws_b, dec=ddec_b, block=dblock, want_argmax=False)
-    eb1.record(stream)
-    torch.cuda.synchronize()
-    t_dir_bf16 = eb0.elapsed_time(eb1) * 1e-3 / 10
-    err_bf16 = float((ddec_b.double() - ddec.double()).abs().max() / ddec.double().max())
+    def side_measurements():
+        """Beside the step, not part of `value`: step-time distribution, device-copy bandwidth,
+        grid hopping on the direct subgrid, the BF16 direct decision, the factorised estimator."""
+        # step-time distribution: each replay bracketed by events (a separate pass, after the timed one)
+        per = []
+        for _ in range(min(args.steps, 50)):
+            a, b = ev(), ev()
+            a.record(stream)
+            graph.replay()
+            b.record(stream)
+            per.append((a, b))
+        torch.cuda.synchronize()
+        step_ms = np.array([a.elapsed_time(b) for a, b in per])
+
+        # device-copy bandwidth (read + write bytes of a 256 MiB copy) as the practical HBM ceiling
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        c0, c1 = ev(), ev()
+        c0.record(stream)
+        for _ in range(10):
+            dst.copy_(src)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        copy_gbs = 2 * src.numel() * 4 * 10 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+        del src, dst
+
+        # grid hopping on the direct method's 64x64x16x16 subgrid: the same points as the direct row
+        sub_dec = torch.empty(tuple(dgrid_s.n), dtype=torch.float32, device=dev)
+        for _ in range(3):
+            gh.rd_maps(radar, y, maps)
+            gh.decision(radar, dgrid, maps, interp, dec=sub_dec, block=dblock, argmax=darg)
+        s0, s1 = ev(), ev()
+        s0.record(stream)
+        for _ in range(20):
+            gh.rd_maps(radar, y, maps)
+            gh.decision(radar, dgrid, maps, interp, dec=sub_dec, block=dblock, argmax=darg)
+        s1.record(stream)
+        torch.cuda.synchronize()
+        t_gh_sub = s0.elapsed_time(s1) * 1e-3 / 20
+
+        # the direct decision with BF16 matrix-core operands, timed on its own (not part of the step)
+        ws_b = torch.empty(gh.direct_workspace_bytes(radar, dgrid, gh.GEMM_BF16), dtype=torch.uint8, device=dev)
+        ddec_b = torch.empty_like(ddec)
+        for _ in range(3):
+            gh.direct_decision(radar, dgrid, y, gemm=gh.GEMM_BF16, ws=ws_b, dec=ddec_b, block=dblock, want_argmax=False)
+        eb0, eb1 = ev(), ev()
+        eb0.record(stream)
+        for _ in range(10):
+            gh.direct_decision(radar, dgrid, y, gemm=gh.GEMM_BF16, ws=ws_b, dec=ddec_b, block=dblock, want_argmax=False)
+        eb1.record(stream)
+        torch.cuda.synchronize()
+        t_dir_bf16 = eb0.elapsed_time(eb1) * 1e-3 / 10
+        err_bf16 = float((ddec_b.double() - ddec.double()).abs().max() / ddec.double().max())
+        return {
+            "ms_per_step_p10_p50_p90": [float(np.percentile(step_ms, q)) for q in (10, 50, 90)],
+            "copy_gbs": copy_gbs,
+            "t_gh_sub": t_gh_sub,
+            "t_dir_bf16": t_dir_bf16,
+            "err_bf16": err_bf16,
+            "factored": factored_timings(gh, torch, radar, grid, y, stream),
+        }
+
     ms_step = wall / args.steps * 1e3
     pts_step = (1 + BOMP_ITERS) * n_gh + n_dir
     sweep_bytes = 4 * n_gh + radar.k * radar.nr * radar.nd * 8 + 16 * nloc
@@ -397,9 +449,8 @@ def main():
         "gh_points_per_s": n_gh / (t_maps + t_sweep + t_arg),
         "gh_sweep_points_per_s": n_gh / t_sweep,
         "direct_points_per_s": n_dir / t_dir,
-        "direct_bf16_points_per_s": n_dir / t_dir_bf16,
-        "direct_bf16_max_rel_diff_vs_f32": err_bf16,
         "speedup_gh_over_direct_per_point": (n_gh / (t_maps + t_sweep + t_arg)) / (n_dir / t_dir),
+        "rd_maps_gbs": (y.numel() * 8 + radar.k * radar.nr * radar.nd * 8) / t_maps / 1e9,
         "roofline": {"kernel": "gh_sweep_columns<bilinear>" if interp == gh.BILINEAR else "gh_sweep_columns<bicubic>",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(),
@@ -407,11 +458,21 @@ def main():
                      "avg_launch_us": t_sweep * 1e6},
     }
 
-    line["factored"] = factored_timings(gh, torch, radar, grid, y, stream)
-    if not args.no_batch:
+    if not args.step_only:
+        x = side_measurements()
+        line.update({
+            "direct_bf16_points_per_s": n_dir / x["t_dir_bf16"],
+            "direct_bf16_max_rel_diff_vs_f32": x["err_bf16"],
+            "speedup_gh_over_direct_same_subgrid": t_dir / x["t_gh_sub"],
+            "ms_per_step_p10_p50_p90": x["ms_per_step_p10_p50_p90"],
+            "copy_gbs": x["copy_gbs"],
+            "factored": x["factored"],
+        })
+        line["roofline"]["frac_of_copy"] = achieved / x["copy_gbs"]
+    if not args.no_batch and not args.step_only:
         line["batch"] = batch_workload(gh, sc, torch, stream)
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.step_only:
         rng = np.random.default_rng(2024)
         gh_idx = rng.integers(0, n_gh, 2_000_000)
         dir_idx = rng.integers(0, n_dir, 100_000)
