@@ -9,12 +9,14 @@
  *
  * Conventions shared by every entry point
  *  - Device pointers (prefix d_) are caller-owned HIP device allocations; the
- *    library never retains a pointer after returning and never allocates
- *    device memory: scratch space comes from caller workspaces whose size the
- *    *_workspace_bytes() queries give.
+ *    library never allocates device memory (scratch space comes from caller
+ *    workspaces whose size the *_workspace_bytes() queries give) and retains
+ *    no pointer after returning, except a gh_batch object, which keeps its
+ *    frame and workspace pointers until gh_batch_destroy.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
- *    Every call only enqueues work; results are valid once the caller has
- *    synchronised the stream, and device faults surface there.
+ *    Every call only enqueues work (gh_batch_create alone also synchronises
+ *    its stream once); results are valid once the caller has synchronised the
+ *    stream, and device faults surface there.
  *  - Arguments are validated on the host before anything is enqueued.  On
  *    error nothing is enqueued, a negative gh_status is returned and
  *    gh_last_error() describes the failure.  No C++ exception crosses the ABI.
