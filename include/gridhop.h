@@ -57,7 +57,7 @@ extern "C" {
 typedef enum {
     GH_OK = 0,
     GH_EINVAL = -1,        /* invalid argument (NULL pointer, bad size, non-finite parameter) */
-    GH_EUNSUPPORTED = -2,  /* valid request outside what this build implements */
+    GH_EUNSUPPORTED = -2,  /* valid request outside what this library implements */
     GH_EHIP = -3,          /* a HIP runtime call failed (no device, launch failure) */
     GH_EWORKSPACE = -4     /* caller workspace smaller than the matching *_workspace_bytes() */
 } gh_status;

@@ -14,8 +14,9 @@ noncoherent sum over receivers, D(x, v) = sum_q |I_q(x, v)|^2, as the direct
 method's objective sums |<Y_q, atom>|^2 over q (eqs. (5)-(6)).
 
 The paper's own choice (polar interpolation in range, nearest neighbour in
-Doppler) is a different index-set/weight rule; bilinear and bicubic are the
-schemes this build ships.
+Doppler) is a different index-set/weight rule, used with the factorised
+decisions of eqs. (5)-(6) in factor.py; the joint 4D decision here uses
+bilinear and bicubic interpolation.
 """
 from __future__ import annotations
 
