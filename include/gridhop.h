@@ -332,9 +332,11 @@ size_t gh_batch_workspace_bytes(const gh_frame *frames, int32_t n_frames);
  * the descriptor table on `stream`, then synchronise that stream once (this
  * call blocks; gh_batch_run never does).  Per frame: the limits of gh_rd_maps
  * and gh_decision, N_d >= 16, Nvy <= 64 and ceil(Nvx / floor(64 / Nvy)) <= 32
- * (a lane's share of the velocity slab); the descriptor table plus the largest
- * Doppler table must fit one wave's 64 KB LDS slice (GH_EUNSUPPORTED
- * otherwise).  interp: GH_INTERP_* for every frame.  d_ws must hold
+ * (a lane's share of the velocity slab); one wave's LDS slice, 768 bytes of
+ * per-receiver coordinate records plus the Doppler table of the largest N_d
+ * (16 bytes per bin bilinear, 32 bicubic), must fit in 64 KB, and so must the
+ * map passes' buffers (GH_EUNSUPPORTED otherwise: N_d = 4096 bilinear,
+ * N_d >= 2048 bicubic).  interp: GH_INTERP_* for every frame.  d_ws must hold
  * gh_batch_workspace_bytes(); its contents belong to the batch until
  * gh_batch_destroy.  *batch receives the new object (NULL on error). */
 int gh_batch_create(const gh_frame *frames, int32_t n_frames, int32_t interp, void *d_ws, size_t ws_bytes,

@@ -257,3 +257,14 @@ def test_factored_argument_checks(lib):
                                     None) == gh.GH_EINVAL
     # the polar rule is for the factorised decision only
     assert lib.gh_decision(rs, g, FAKE, 0, gh.POLAR, None, FAKE, None, None) == gh.GH_EINVAL
+
+
+def test_batch_lds_limits(lib):
+    """A wave's LDS slice (768 B of coordinate records + 16 or 32 B per Doppler bin) must fit 64 KB."""
+    out = ctypes.c_void_p()
+    big = 1 << 40
+    fr, keep = batch_frames([(3, 64, 1024, 4, (4, 4, 4, 4))])          # N_d = 4096
+    assert lib.gh_batch_create(fr, 1, gh.BILINEAR, FAKE, big, ctypes.byref(out), None) == gh.GH_EUNSUPPORTED
+    fr, keep = batch_frames([(3, 64, 512, 4, (4, 4, 4, 4))])           # N_d = 2048
+    assert lib.gh_batch_create(fr, 1, gh.BICUBIC, FAKE, big, ctypes.byref(out), None) == gh.GH_EUNSUPPORTED
+    assert "LDS" in gh.last_error()
