@@ -268,3 +268,13 @@ def test_batch_lds_limits(lib):
     fr, keep = batch_frames([(3, 64, 512, 4, (4, 4, 4, 4))])           # N_d = 2048
     assert lib.gh_batch_create(fr, 1, gh.BICUBIC, FAKE, big, ctypes.byref(out), None) == gh.GH_EUNSUPPORTED
     assert "LDS" in gh.last_error()
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """No fallback: without the built library every entry point raises instead of computing elsewhere."""
+    monkeypatch.setattr(gh, "_lib", None)
+    monkeypatch.setattr(gh, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libgridhop.so"))
+    with pytest.raises(ImportError):
+        gh.load()
+    with pytest.raises(ImportError):
+        gh.last_error()
