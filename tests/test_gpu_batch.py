@@ -221,6 +221,32 @@ def test_batch_graph_replays_match_eager():
     b.close()
 
 
+def test_batching_workload_bicubic_against_single_frames():
+    """The 64-frame workload with Keys bicubic interpolation: every frame's block maxima and
+    argmax against the single-frame decision (bit for bit where both use the column
+    arithmetic, else within 1e-5 of the maximum)."""
+    scenes = sc.make_batch()
+    b = gh.Batch.from_scenes(scenes, gh.BICUBIC)
+    b.run()
+    torch.cuda.synchronize()
+    am = gh.decode_peaks(b.argmax)
+    for i, s in enumerate(scenes):
+        r = gh.Radar.from_scene(s)
+        z = gh.rd_maps(r, b.ys[i])
+        dec, block, a1 = gh.decision(r, gh.grid_of(s.grid), z, gh.BICUBIC)
+        bv, _ = gh.decode_peaks(b.blocks[i])
+        sv, _ = gh.decode_peaks(block)
+        v1, i1 = gh.decode_peaks(a1)
+        if columns_shape(s.grid.n):
+            assert np.array_equal(bv, sv), i
+            assert am[1][i] == i1[0], i
+        else:
+            assert np.max(np.abs(bv - sv)) <= DEC_TOL * v1[0], i
+            if am[1][i] != i1[0]:
+                assert float(dec.view(-1)[int(am[1][i])]) >= (1 - TIE_TOL) * v1[0], i
+    b.close()
+
+
 def test_batching_workload():
     """The batching workload: 64 seeded frames of mixed shapes (K 3..8, Ms 128/256,
     Mc 64/128, grids 64^2..192^2 x 16^2..32^2), autotuned, then replayed as a graph.

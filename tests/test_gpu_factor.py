@@ -94,14 +94,14 @@ def test_range_spectra_parity(cfg, centered):
 
 
 @pytest.mark.parametrize("kind", KINDS)
-@pytest.mark.parametrize("cfg", [1, 2])
+@pytest.mark.parametrize("cfg", [1, 2, 5])
 def test_factored_grid_hopping_parity(cfg, kind):
     s = sc.make_scene(cfg, 0)
     compare(s, ord_.radar_from_scene(s), gh.Radar.from_scene(s), gh.FACTOR_GH, kind, label=f"gh cfg={cfg} kind={kind}")
 
 
 @pytest.mark.parametrize("gemm,tol", [(gh.GEMM_F32, TOL), (gh.GEMM_BF16, BF16_TOL)])
-@pytest.mark.parametrize("cfg", [1, 2])
+@pytest.mark.parametrize("cfg", [1, 2, 5])
 def test_factored_direct_parity(cfg, gemm, tol):
     s = sc.make_scene(cfg, 0)
     compare(s, ord_.radar_from_scene(s), gh.Radar.from_scene(s), gh.FACTOR_DIRECT, gemm=gemm, tol=tol,
