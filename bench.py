@@ -95,13 +95,31 @@ def parse():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this size (HBM counter calibration) and exit")
     ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-parallel", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
 # ----------------------------------------------------------------------------- CPU baseline (oracle)
 
-def cpu_worker(path):
-    """Child process: time the FP64 oracle on a bounded sample; compare with the GPU samples."""
+_POOL_ARGS = {}
+
+
+def _pool_gh(lo, hi):
+    a = _POOL_ARGS
+    from oracle import gh as ogh
+    return ogh.gh_points(a["z"], a["r"], *(p[lo:hi] for p in a["pts"]), a["interp"])
+
+
+def _pool_dir(lo, hi):
+    a = _POOL_ARGS
+    from oracle import direct as odirect
+    return odirect.direct_points(a["y"], a["r"], *(p[lo:hi] for p in a["dpts"]))
+
+
+def cpu_worker(path, parallel=False):
+    """Child process: time the FP64 oracle on a bounded sample; compare with the GPU samples.
+    With `parallel`, the sampled grid-hopping and direct points are split over a process
+    pool of every core the process may use (the oracle itself unchanged)."""
     import numpy as np
 
     from oracle import bomp as obomp, direct as odirect, gh as ogh, maps as omaps
@@ -126,15 +144,30 @@ def cpu_worker(path):
 
     gh_idx = job["gh_idx"]
     pts = points(grid, gh_idx)
-    t0 = time.perf_counter()
-    gh_ref = ogh.gh_points(z, r, *pts, interp)
-    t_gh_pt = (time.perf_counter() - t0) / len(gh_idx)
-
     d_idx = job["dir_idx"]
     dpts = points(dgrid, d_idx)
-    t0 = time.perf_counter()
-    dir_ref = odirect.direct_points(s.y, r, *dpts)
-    t_dir_pt = (time.perf_counter() - t0) / len(d_idx)
+    cores = len(os.sched_getaffinity(0)) if parallel else 1
+    if parallel:
+        import multiprocessing as mp
+        _POOL_ARGS.update(z=z, r=r, pts=pts, dpts=dpts, y=s.y, interp=interp)
+        ctx = mp.get_context("fork")     # workers inherit the oracle's inputs; nothing large is pickled
+        with ctx.Pool(cores) as pool:
+            def split(n):
+                b = np.linspace(0, n, 4 * cores + 1).astype(int)
+                return list(zip(b[:-1], b[1:]))
+            t0 = time.perf_counter()
+            gh_ref = np.concatenate(pool.starmap(_pool_gh, split(len(gh_idx))))
+            t_gh_pt = (time.perf_counter() - t0) / len(gh_idx)
+            t0 = time.perf_counter()
+            dir_ref = np.concatenate(pool.starmap(_pool_dir, split(len(d_idx))))
+            t_dir_pt = (time.perf_counter() - t0) / len(d_idx)
+    else:
+        t0 = time.perf_counter()
+        gh_ref = ogh.gh_points(z, r, *pts, interp)
+        t_gh_pt = (time.perf_counter() - t0) / len(gh_idx)
+        t0 = time.perf_counter()
+        dir_ref = odirect.direct_points(s.y, r, *dpts)
+        t_dir_pt = (time.perf_counter() - t0) / len(d_idx)
 
     support = [int(c) for c in job["support"]]
     t0 = time.perf_counter()
@@ -153,11 +186,12 @@ def cpu_worker(path):
     out = {
         "value": ((1 + BOMP_ITERS) * n_gh + n_dir) / t_step,
         "unit": "grid points/s",
-        "cores": 1,
+        "cores": cores,
         "kind": "oracle",
-        "sample": (f"FP64 numpy oracle, 1 thread: maps of the frame, grid hopping at {len(gh_idx)} points, "
+        "sample": (f"FP64 numpy oracle, {'a pool of ' + str(cores) + ' processes of 1 thread for the sampled points' if parallel else '1 thread'}: "
+                   f"maps of the frame, grid hopping at {len(gh_idx)} points, "
                    f"direct at {len(d_idx)} points, BOMP fits for supports of 1..{len(support)}, one refinement; "
-                   f"per-point and per-call times scaled to the step ({sampled:.1f} s of CPU work measured)"),
+                   f"per-point and per-call times scaled to the step ({sampled:.1f} s measured)"),
         "step_seconds_estimate": t_step,
         "gh_points_per_s": 1.0 / t_gh_pt,
         "direct_points_per_s": 1.0 / t_dir_pt,
@@ -167,7 +201,7 @@ def cpu_worker(path):
     print(json.dumps(out))
 
 
-def cpu_baseline(job):
+def cpu_baseline(job, parallel=False):
     import numpy as np
     fd, path = tempfile.mkstemp(suffix=".npz")
     os.close(fd)
@@ -175,8 +209,8 @@ def cpu_baseline(job):
         np.savez(path, **job)
         env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
                    HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
-        res = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-worker", path],
-                             capture_output=True, text=True, env=env, timeout=600)
+        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-worker", path] + (["--cpu-parallel"] if parallel else [])
+        res = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=600)
         if res.returncode != 0:
             return {"error": res.stderr[-2000:]}
         return json.loads(res.stdout.strip().splitlines()[-1])
@@ -242,7 +276,7 @@ def batch_workload(gh, sc, torch, stream):
 def main():
     args = parse()
     if args.cpu_worker:
-        cpu_worker(args.cpu_worker)
+        cpu_worker(args.cpu_worker, args.cpu_parallel)
         return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -484,6 +518,7 @@ def main():
                "dir_max": np.float64(ddv.max()), "support": bomp.support.cpu().numpy(),
                "interp": np.int64(interp)}
         line["cpu_baseline"] = cpu_baseline(job)
+        line["cpu_baseline_all_cores"] = cpu_baseline(job, parallel=True)
     print(json.dumps(line), flush=True)
     return 0
 
