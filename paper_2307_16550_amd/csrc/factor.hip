@@ -17,11 +17,12 @@
 //      geometry and range taps of receiver q come from lane q (FP64) by
 //      shuffles; writes E and a block peak (E, location) per location;
 //   2. the argmax of the block peaks into result[0] (ties to the lowest index);
-//   3. velocity: one wave per 64 velocity points; per receiver the wave puts
-//      g at the selected location in LDS and every lane sums its point's
-//      Doppler correlation (phases in 32-bit fixed point, an exact anchor
-//      every eight chirps and a rotation in between); writes V and a peak
-//      per wave with the 4D index;
+//   3. velocity: 32 velocity points per workgroup, 8 lanes per point; per
+//      receiver the workgroup puts g at the selected location in LDS, lane c
+//      of a point sums the chirps m = c mod 8 of its Doppler correlation
+//      (phases in 32-bit fixed point, an exact anchor every eight terms and a
+//      rotation in between) and shuffles reduce the eight partial sums;
+//      writes V and a peak per workgroup with the 4D index;
 //   4. the argmax of those peaks into result[1].
 #include "gh_internal.h"
 
@@ -29,8 +30,10 @@ namespace gh {
 namespace {
 
 constexpr int kLocWaves = 4;
-constexpr int kVelThreads = 64;
-constexpr int kRunF = 8;    // chirps per exact phase anchor
+constexpr int kVelThreads = 256;
+constexpr int kVelLanes = 8;                              // lanes per velocity point (chirp classes mod 8)
+constexpr int kVelPoints = kVelThreads / kVelLanes;       // velocity points per workgroup
+constexpr int kRunF = 8;    // terms per exact phase anchor
 
 struct RangeTaps {
     int row[4];     // range bin index within one period
@@ -167,13 +170,16 @@ __global__ __launch_bounds__(kVelThreads) void velocity_at_peak(Geom g, GridP gp
                                                                float* __restrict__ vel_out,
                                                                gh_peak* __restrict__ vpeaks) {
     extern __shared__ float2 gvec[];   // [Mc]
+    __shared__ float red_v[kVelThreads / 64];
+    __shared__ int red_i[kVelThreads / 64];
     constexpr int kTaps = taps_of<KIND>();
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int cls = tid & (kVelLanes - 1);                 // this lane's chirps: m = cls mod 8
     // a selection outside the grid (every energy NaN: non-finite input) reads location 0
     const int loc = (sel->index >= 0 && sel->index < gp.nloc) ? (int)sel->index : 0;
     const int ix = loc / gp.n[1], iy = loc - ix * gp.n[1];
     const double x = gp.lo[0] + ix * gp.step[0], y = gp.lo[1] + iy * gp.step[1];
-    const int v = blockIdx.x * kVelThreads + lane;
+    const int v = blockIdx.x * kVelPoints + tid / kVelLanes;
     const bool live = v < gp.nv;
     const int ivx = live ? v / gp.n[3] : 0, ivy = live ? v - ivx * gp.n[3] : 0;
     const double vx = gp.lo[2] + ivx * gp.step[2], vy = gp.lo[3] + ivy * gp.step[3];
@@ -184,11 +190,11 @@ __global__ __launch_bounds__(kVelThreads) void velocity_at_peak(Geom g, GridP gp
         bistatic(g, q, x, y, r, wx, wy);
         if (METHOD == GH_FACTOR_DIRECT) {
             const float2* gq = input + ((size_t)q * gp.nloc + loc) * mc;
-            for (int m = lane; m < mc; m += kVelThreads) gvec[m] = gq[m];
+            for (int m = tid; m < mc; m += kVelThreads) gvec[m] = gq[m];
         } else {
             const RangeTaps t = range_taps<KIND>(g, g.kr * r, theta);
             const float2* sq = input + (size_t)q * g.nr * mc;
-            for (int m = lane; m < mc; m += kVelThreads) {
+            for (int m = tid; m < mc; m += kVelThreads) {
                 float re = 0.f, im = 0.f;
 #pragma unroll
                 for (int u = 0; u < kTaps; ++u) {
@@ -208,26 +214,40 @@ __global__ __launch_bounds__(kVelThreads) void velocity_at_peak(Geom g, GridP gp
             const long long l = (long long)floor(g.kd * rate + 0.5);   // nearest Doppler bin
             dph = (uint32_t)((unsigned long long)l << (32 - g.log2_nd));
         }
-        const float2 rot = expm_fixed(dph);
+        const float2 rot = expm_fixed(dph * (uint32_t)kVelLanes);
         float cre = 0.f, cim = 0.f;
-        for (int m0 = 0; m0 < mc; m0 += kRunF) {
+        for (int m0 = cls; m0 < mc; m0 += kVelLanes * kRunF) {
             float2 e = expm_fixed(dph * (uint32_t)m0);
 #pragma unroll
             for (int u = 0; u < kRunF; ++u) {
-                const float2 z = gvec[m0 + u];
-                cre = fmaf(z.x, e.x, fmaf(-z.y, e.y, cre));
-                cim = fmaf(z.x, e.y, fmaf(z.y, e.x, cim));
+                const int m = m0 + u * kVelLanes;
+                if (m < mc) {
+                    const float2 z = gvec[m];
+                    cre = fmaf(z.x, e.x, fmaf(-z.y, e.y, cre));
+                    cim = fmaf(z.x, e.y, fmaf(z.y, e.x, cim));
+                }
                 e = cmul(e, rot);
             }
+        }
+#pragma unroll
+        for (int off = 1; off < kVelLanes; off <<= 1) {
+            cre += __shfl_xor(cre, off, 64);
+            cim += __shfl_xor(cim, off, 64);
         }
         acc = fmaf(cre, cre, fmaf(cim, cim, acc));
         __syncthreads();   // gvec is rewritten for the next receiver
     }
-    if (live && vel_out) vel_out[v] = acc;
+    if (live && cls == 0 && vel_out) vel_out[v] = acc;
     float bv = live ? acc : -INFINITY;
     int bi = live ? v : 0x7fffffff;
     wave_peak(bv, bi);
-    if (lane == 0) {
+    if ((tid & 63) == 0) {
+        red_v[tid >> 6] = bv;
+        red_i[tid >> 6] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < kVelThreads / 64; ++w) peak_merge(bv, bi, red_v[w], red_i[w]);
         gh_peak p;
         p.value = bv;
         p.reserved = 0;
@@ -238,7 +258,7 @@ __global__ __launch_bounds__(kVelThreads) void velocity_at_peak(Geom g, GridP gp
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-int velocity_groups(const GridP& gp) { return (gp.nv + kVelThreads - 1) / kVelThreads; }
+int velocity_groups(const GridP& gp) { return (gp.nv + kVelPoints - 1) / kVelPoints; }
 
 template <int METHOD, int KIND>
 void launch_velocity(const Geom& g, const GridP& gp, double theta, const float2* input, const gh_peak* sel,
