@@ -8,7 +8,9 @@
 //   with the Dirichlet sum Dir(d; M) = sum_{n<M} exp(j 2 pi d n) in closed form;
 //   residual Y_q - sum_t alpha_t A_q(theta_t).
 // The right-hand side is spread over workgroups of 8 chirps (separable atoms,
-// FP32 products over a chirp, FP64 from there on) and summed in a fixed order.
+// FP32 products over a chirp, FP64 from there on) and summed in a fixed order;
+// the residual's workgroups each solve the small system themselves (identical
+// inputs, identical order, so identical alpha), which saves a launch.
 #include "gh_internal.h"
 
 namespace gh {
@@ -35,6 +37,7 @@ __device__ dcplx dirichlet(double d, int m) {
 
 constexpr int kRowsPerChunk = 8;          // chirps per workgroup of the right-hand side
 constexpr int kTabEntries = 4096;         // range phase factors per atom group (32 KiB)
+constexpr int kResidWorkgroups = 1024;    // residual grid cap: four workgroups per CU
 
 // Sensed frequencies (cycles per sample, per chirp) of grid cell idx at receiver q.
 __device__ __forceinline__ void cell_freqs(const Geom& g, const GridP& gp, int q, int64_t idx, double& fr, double& fd) {
@@ -116,23 +119,25 @@ __global__ __launch_bounds__(kThreads) void bomp_rhs_kernel(Geom g, GridP gp, co
     }
 }
 
-// One workgroup per receiver: sums the right-hand side partials, Gram,
-// Cholesky solve.  Writes alpha (complex64 [nsel][K]) and the fixed-point
-// phases of the selected atoms.
-__global__ __launch_bounds__(kThreads) void bomp_fit_kernel(Geom g, GridP gp, const int64_t* __restrict__ support,
-                                                           int nsel, const double2* __restrict__ part,
-                                                           float2* __restrict__ alpha, uint32_t* __restrict__ phases) {
-    __shared__ double fr[kMaxSupport], fd[kMaxSupport];
-    __shared__ uint32_t frx[kMaxSupport], fdx[kMaxSupport];
-    __shared__ dcplx rhs[kMaxSupport];
-    __shared__ dcplx gram[kMaxSupport][kMaxSupport];
-    __shared__ dcplx z[kMaxSupport];
-    const int q = blockIdx.x;
+// Least squares of receiver q (called by a whole workgroup): sums the
+// right-hand side partials, builds the Gram matrix in closed form and solves by
+// Cholesky (thread 0, FP64).  Leaves alpha in sh_z and the fixed-point phases
+// of the atoms in sh_frx / sh_fdx.
+struct FitShared {
+    double fr[kMaxSupport], fd[kMaxSupport];
+    uint32_t frx[kMaxSupport], fdx[kMaxSupport];
+    dcplx rhs[kMaxSupport];
+    dcplx gram[kMaxSupport][kMaxSupport];
+    dcplx z[kMaxSupport];
+};
+
+__device__ void solve_fit(const Geom& g, const GridP& gp, int q, const int64_t* __restrict__ support, int nsel,
+                          const double2* __restrict__ part, FitShared& sh) {
     const int tid = threadIdx.x;
     if (tid < nsel) {
-        cell_freqs(g, gp, q, support[tid], fr[tid], fd[tid]);
-        frx[tid] = cycles_to_fixed(fr[tid]);
-        fdx[tid] = cycles_to_fixed(fd[tid]);
+        cell_freqs(g, gp, q, support[tid], sh.fr[tid], sh.fd[tid]);
+        sh.frx[tid] = cycles_to_fixed(sh.fr[tid]);
+        sh.fdx[tid] = cycles_to_fixed(sh.fd[tid]);
         const int nchunk = g.mc / kRowsPerChunk;
         double2 acc = make_double2(0.0, 0.0);
         for (int c = 0; c < nchunk; ++c) {
@@ -140,100 +145,107 @@ __global__ __launch_bounds__(kThreads) void bomp_fit_kernel(Geom g, GridP gp, co
             acc.x += v.x;
             acc.y += v.y;
         }
-        rhs[tid] = {acc.x, acc.y};
+        sh.rhs[tid] = {acc.x, acc.y};
     }
     __syncthreads();
-    for (int e = tid; e < nsel * nsel; e += kThreads) {
+    for (int e = tid; e < nsel * nsel; e += blockDim.x) {
         const int t = e / nsel, u = e - t * nsel;
-        gram[t][u] = dmul(dirichlet(fr[u] - fr[t], g.ms), dirichlet(fd[u] - fd[t], g.mc));
+        sh.gram[t][u] = dmul(dirichlet(sh.fr[u] - sh.fr[t], g.ms), dirichlet(sh.fd[u] - sh.fd[t], g.mc));
     }
     __syncthreads();
     if (tid == 0) {
         // Cholesky G = L L^H (lower, in place), then L z = rhs, L^H x = z.
         for (int j = 0; j < nsel; ++j) {
-            double d = gram[j][j].x;
-            for (int k = 0; k < j; ++k) d -= gram[j][k].x * gram[j][k].x + gram[j][k].y * gram[j][k].y;
+            double d = sh.gram[j][j].x;
+            for (int k = 0; k < j; ++k) d -= sh.gram[j][k].x * sh.gram[j][k].x + sh.gram[j][k].y * sh.gram[j][k].y;
             d = sqrt(d > 0.0 ? d : 1e-300);
-            gram[j][j] = {d, 0.0};
+            sh.gram[j][j] = {d, 0.0};
             for (int i = j + 1; i < nsel; ++i) {
-                dcplx s = gram[i][j];
+                dcplx s = sh.gram[i][j];
                 for (int k = 0; k < j; ++k) {
-                    const dcplx p = dconjmul(gram[j][k], gram[i][k]);   // L[i][k] conj(L[j][k])
+                    const dcplx p = dconjmul(sh.gram[j][k], sh.gram[i][k]);   // L[i][k] conj(L[j][k])
                     s.x -= p.x;
                     s.y -= p.y;
                 }
-                gram[i][j] = {s.x / d, s.y / d};
+                sh.gram[i][j] = {s.x / d, s.y / d};
             }
         }
         for (int i = 0; i < nsel; ++i) {
-            dcplx s = rhs[i];
+            dcplx s = sh.rhs[i];
             for (int k = 0; k < i; ++k) {
-                const dcplx p = dmul(gram[i][k], z[k]);
+                const dcplx p = dmul(sh.gram[i][k], sh.z[k]);
                 s.x -= p.x;
                 s.y -= p.y;
             }
-            z[i] = {s.x / gram[i][i].x, s.y / gram[i][i].x};
+            sh.z[i] = {s.x / sh.gram[i][i].x, s.y / sh.gram[i][i].x};
         }
         for (int i = nsel - 1; i >= 0; --i) {
-            dcplx s = z[i];
+            dcplx s = sh.z[i];
             for (int k = i + 1; k < nsel; ++k) {
-                const dcplx p = dconjmul(gram[k][i], z[k]);   // conj(L[k][i]) x[k]
+                const dcplx p = dconjmul(sh.gram[k][i], sh.z[k]);   // conj(L[k][i]) x[k]
                 s.x -= p.x;
                 s.y -= p.y;
             }
-            z[i] = {s.x / gram[i][i].x, s.y / gram[i][i].x};
-        }
-        for (int t = 0; t < nsel; ++t) {
-            alpha[(size_t)t * g.k + q] = make_float2((float)z[t].x, (float)z[t].y);
-            phases[((size_t)t * g.k + q) * 2] = frx[t];
-            phases[((size_t)t * g.k + q) * 2 + 1] = fdx[t];
+            sh.z[i] = {s.x / sh.gram[i][i].x, s.y / sh.gram[i][i].x};
         }
     }
+    __syncthreads();
 }
 
-// resid[q][m][s] = y[q][m][s] - sum_t alpha[t][q] exp(+j 2 pi (f_r,t s + f_d,t m))
-__global__ __launch_bounds__(kThreads) void bomp_residual_kernel(Geom g, const float2* __restrict__ y,
-                                                                float2* __restrict__ resid,
-                                                                const float2* __restrict__ alpha,
-                                                                const uint32_t* __restrict__ phases, int nsel) {
+// Fit and residual of receiver blockIdx.y: every workgroup solves the (small)
+// least squares itself, workgroup 0 also writes alpha (complex64 [nsel][K]), then
+//   resid[q][m][s] = y[q][m][s] - sum_t alpha[t][q] exp(+j 2 pi (f_r,t s + f_d,t m)).
+__global__ __launch_bounds__(kThreads) void bomp_fit_residual_kernel(Geom g, GridP gp, const float2* __restrict__ y,
+                                                                    float2* __restrict__ resid,
+                                                                    const int64_t* __restrict__ support, int nsel,
+                                                                    const double2* __restrict__ part,
+                                                                    float2* __restrict__ alpha) {
+    __shared__ FitShared sh;
+    __shared__ float2 al[kMaxSupport];
     const int q = blockIdx.y;
-    const int n = g.mc * g.ms;
-    const int e = blockIdx.x * kThreads + threadIdx.x;
-    if (e >= n) return;
-    const uint32_t m = (uint32_t)(e >> g.log2_ms), s = (uint32_t)(e & (g.ms - 1));
-    float2 v = y[(size_t)q * n + e];
-    for (int t = 0; t < nsel; ++t) {
-        const size_t o = (size_t)t * g.k + q;
-        const float2 em = expm_fixed(phases[2 * o] * s + phases[2 * o + 1] * m);   // exp(-j ...)
-        const float2 at = make_float2(em.x, -em.y);                                 // exp(+j ...)
-        const float2 al = alpha[o];
-        v.x -= al.x * at.x - al.y * at.y;
-        v.y -= al.x * at.y + al.y * at.x;
+    solve_fit(g, gp, q, support, nsel, part, sh);
+    if (threadIdx.x < nsel) {
+        const float2 a = make_float2((float)sh.z[threadIdx.x].x, (float)sh.z[threadIdx.x].y);
+        al[threadIdx.x] = a;
+        if (blockIdx.x == 0) alpha[(size_t)threadIdx.x * g.k + q] = a;
     }
-    resid[(size_t)q * n + e] = v;
+    __syncthreads();
+    const int n = g.mc * g.ms;
+    for (int e = blockIdx.x * kThreads + threadIdx.x; e < n; e += gridDim.x * kThreads) {
+        const uint32_t m = (uint32_t)(e >> g.log2_ms), s = (uint32_t)(e & (g.ms - 1));
+        float2 v = y[(size_t)q * n + e];
+        for (int t = 0; t < nsel; ++t) {
+            const float2 em = expm_fixed(sh.frx[t] * s + sh.fdx[t] * m);   // exp(-j ...)
+            const float2 at = make_float2(em.x, -em.y);                     // exp(+j ...)
+            const float2 a = al[t];
+            v.x -= a.x * at.x - a.y * at.y;
+            v.y -= a.x * at.y + a.y * at.x;
+        }
+        resid[(size_t)q * n + e] = v;
+    }
 }
 
 }  // namespace
 
 size_t bomp_fit_ws_bytes(const Geom& g) {
-    return (size_t)g.k * (g.mc / kRowsPerChunk) * kMaxSupport * sizeof(double2) +
-           (size_t)kMaxSupport * g.k * 2 * sizeof(uint32_t);
+    return (size_t)g.k * (g.mc / kRowsPerChunk) * kMaxSupport * sizeof(double2);
 }
 
 hipError_t launch_bomp_fit(const Geom& g, const GridP& gp, const float2* y, float2* resid, const int64_t* support,
                            int nsel, float2* alpha, void* ws, hipStream_t st) {
     double2* part = static_cast<double2*>(ws);
-    uint32_t* phases = reinterpret_cast<uint32_t*>(part + (size_t)g.k * (g.mc / kRowsPerChunk) * kMaxSupport);
     hipLaunchKernelGGL(bomp_rhs_kernel, dim3(g.mc / kRowsPerChunk, g.k), dim3(kThreads), 0, st, g, gp, y, support,
                        nsel, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(bomp_fit_kernel, dim3(g.k), dim3(kThreads), 0, st, g, gp, support, nsel, part, alpha, phases);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    // At most kResidWorkgroups workgroups in all (each holds about 18 KiB of LDS),
+    // so the whole grid is resident at once and the solve's latency is paid once.
     const int n = g.mc * g.ms;
-    hipLaunchKernelGGL(bomp_residual_kernel, dim3((n + kThreads - 1) / kThreads, g.k), dim3(kThreads), 0, st, g, y,
-                       resid, alpha, phases, nsel);
+    int per_q = (n + kThreads - 1) / kThreads;
+    const int cap = kResidWorkgroups / g.k > 0 ? kResidWorkgroups / g.k : 1;
+    if (per_q > cap) per_q = cap;
+    hipLaunchKernelGGL(bomp_fit_residual_kernel, dim3(per_q, g.k), dim3(kThreads), 0, st, g, gp, y, resid, support,
+                       nsel, part, alpha);
     return hipGetLastError();
 }
 
