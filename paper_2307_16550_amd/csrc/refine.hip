@@ -516,9 +516,10 @@ __global__ __launch_bounds__(kThreads) void refine_single_kernel(Geom g, GridP g
 // launch's cells, whose estimates are then NaN).
 
 constexpr int kCT = 512;             // threads of a cluster workgroup
-constexpr int kCand = 4;             // points per pass
+constexpr int kCand = 8;             // points per pass
 constexpr int kRowsMaxC = kCT / kCand;   // rows per workgroup (one thread per (point, row))
 constexpr int kRowsMinC = kCT / 64;      // at most 64 lanes per row
+constexpr int kInFlight = 32 / kCand;    // frame loads in flight per lane
 constexpr int kWgsTarget = 32;       // preferred workgroups per cell
 constexpr int kErMax = 8192;         // range phase factors per pass (64 KB of LDS)
 constexpr int kSlotsMax = 4096;      // workgroups per launch (partial-buffer slots)
@@ -532,7 +533,7 @@ struct Cluster {
 
 struct ClusterShared {
     float2 ed[kCand][kRowsMaxC];          // Doppler phase factor [point][row]
-    double2 a[kCand][3][kRowsMaxC];       // A_p [point][p][row]
+    float2 a[kCand][3][kRowsMaxC];        // A_p [point][p][row] (FP32 sums)
     double red[kCand][kRowsMaxC / 8][12]; // per-lane-group partial moments
     double mom[kCand][kMaxRx][12];        // the cell's moments at each point of the pass
     double cur[kMaxRx][12];               // moments at the current point
@@ -614,16 +615,16 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
         if (row < cx.nrows) {
             const float2* yr = y + (size_t)(cx.r0 + row) * ms;
             const int eoff = (((cx.r0 + row) >> g.log2_mc) - cx.q_lo) * ms;
-            // eight independent loads in flight per lane, then their products
-            for (int s0 = lane; s0 < ms; s0 += 8 * tpr) {
-                float2 v[8];
+            // kInFlight independent loads per lane, then their products (in sample order)
+            for (int s0 = lane; s0 < ms; s0 += kInFlight * tpr) {
+                float2 v[kInFlight];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
+                for (int k = 0; k < kInFlight; ++k) {
                     const int s = s0 + k * tpr;
                     v[k] = s < ms ? yr[s] : make_float2(0.f, 0.f);
                 }
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
+                for (int k = 0; k < kInFlight; ++k) {
                     const int s = s0 + k * tpr;
                     if (s < ms) {
                         const float fs = (float)s, fs2 = fs * fs;
@@ -659,7 +660,7 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
 #pragma unroll
             for (int c = 0; c < kCand; ++c)
 #pragma unroll
-                for (int p = 0; p < 3; ++p) sh.a[c][p][row] = make_double2(acc[c][2 * p], acc[c][2 * p + 1]);
+                for (int p = 0; p < 3; ++p) sh.a[c][p][row] = make_float2(acc[c][2 * p], acc[c][2 * p + 1]);
         }
     }
     __syncthreads();
@@ -674,7 +675,8 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
             const double dm = (double)((cx.r0 + row) & (mc - 1));
 #pragma unroll
             for (int p = 0; p < 3; ++p) {
-                const double2 a = sh.a[c][p][row];
+                const float2 af = sh.a[c][p][row];
+                const double2 a = make_double2(af.x, af.y);
                 const double re = a.x * e.x - a.y * e.y;
                 const double im = a.x * e.y + a.y * e.x;
                 if (p == 0) {
