@@ -29,6 +29,42 @@ namespace {
 constexpr int kThreads = 1024;
 constexpr double kTol = 1e-7;
 
+// Sums over aligned groups of n lanes (n a power of two, at most 64) into each
+// group's first lane; the other lanes are left with partial sums.  Within a
+// row of 16 lanes, lane i adds lane i + K read by a DPP row shift (lanes past
+// the row's end read zero); across rows, lane shuffles.
+template <int K>
+__device__ __forceinline__ float from_lane_above(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + K, 0xf, 0xf, true));
+}
+template <int K>
+__device__ __forceinline__ double from_lane_above(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x100 + K, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x100 + K, 0xf, 0xf, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int K, typename T, int N>
+__device__ __forceinline__ void add_lane_above(T (&v)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += from_lane_above<K>(v[i]);
+}
+template <typename T, int N>
+__device__ __forceinline__ void group_sum_to_first(T (&v)[N], int n) {
+    if (n > 1) add_lane_above<1>(v);
+    if (n > 2) add_lane_above<2>(v);
+    if (n > 4) add_lane_above<4>(v);
+    if (n > 8) add_lane_above<8>(v);
+    if (n > 16) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] += __shfl_down(v[i], 16, 64);
+    }
+    if (n > 32) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] += __shfl_down(v[i], 32, 64);
+    }
+}
+
 // f_r, f_d and their first and second derivatives, kept to the structurally
 // nonzero entries: f_r depends on (x, y) only, f_d is linear in v, and
 // d2 f_d / dx dv = beta_d J with J symmetric.
@@ -520,7 +556,7 @@ constexpr int kCand = 8;             // points per pass
 constexpr int kRowsMaxC = kCT / kCand;   // rows per workgroup (one thread per (point, row))
 constexpr int kRowsMinC = kCT / 64;      // at most 64 lanes per row
 constexpr int kInFlight = 32 / kCand;    // frame loads in flight per lane
-constexpr int kWgsTarget = 32;       // preferred workgroups per cell
+constexpr int kWgsTarget = 16;       // preferred workgroups per cell
 constexpr int kErMax = 8192;         // range phase factors per pass (64 KB of LDS)
 constexpr int kSlotsMax = 4096;      // workgroups per launch (partial-buffer slots)
 constexpr unsigned kSpinLimit = 1u << 21;
@@ -646,16 +682,7 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
                 }
             }
         }
-        // level by level, so the shuffles of one level are independent
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            if (off < tpr) {
-#pragma unroll
-                for (int c = 0; c < kCand; ++c)
-#pragma unroll
-                    for (int i = 0; i < 6; ++i) acc[c][i] += __shfl_xor(acc[c][i], off, 64);
-            }
-        }
+        group_sum_to_first(reinterpret_cast<float(&)[kCand * 6]>(acc), tpr);
         if (lane == 0) {
 #pragma unroll
             for (int c = 0; c < kCand; ++c)
@@ -699,13 +726,7 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
         }
         const int seg = R < mc ? R : mc;               // rows of one receiver in this workgroup
         const int gsz = seg < 64 ? seg : 64;           // of which one lane group of a wave
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            if (off < gsz) {
-#pragma unroll
-                for (int i = 0; i < 12; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
-            }
-        }
+        group_sum_to_first(acc, gsz);
         if (c < kCand && (row & (gsz - 1)) == 0) {
 #pragma unroll
             for (int i = 0; i < 12; ++i) sh.red[c][row / gsz][i] = acc[i];
