@@ -352,6 +352,22 @@ def test_refine_parity(cfg, trial, kernel, monkeypatch):
     assert np.max(np.abs(tg[:, 2:] - tr[:, 2:])) <= 1e-3
 
 
+@pytest.mark.parametrize("rows", [4, 8, 16, 32, 64])
+def test_refine_rows_per_workgroup(rows, monkeypatch):
+    """Cluster splits of the paper-scale frame from the fewest to the most rows per
+    workgroup (requests outside the supported splits are clamped to them), i.e.
+    every depth of the in-workgroup sums."""
+    say(f"refine rows per workgroup {rows}")
+    monkeypatch.setenv("GH_REFINE_ROWS", str(rows))
+    s, r, gr = scene_and_radar(2, 0)
+    cells = [true_cell(s, t) for t in range(s.pos.shape[0])]
+    th = gh.refine(gr, gh.grid_of(s.grid), to_dev(s.y), torch.tensor(cells, dtype=torch.int64, device=dev()))
+    tg = th.cpu().numpy()
+    tr = orefine.refine(s.y, r, s.grid, cells)
+    assert np.all(np.isfinite(tg))
+    assert np.max(np.abs(tg - tr)) <= 1e-3, (tg, tr)
+
+
 def test_refine_noise_free_truth():
     s, r, gr = scene_and_radar(1, 12, snr_db=math.inf)
     th = gh.refine(gr, gh.grid_of(s.grid), to_dev(s.y),
