@@ -49,6 +49,8 @@ sys.path.insert(0, ROOT)
 
 CFG = 2
 HBM_PEAK_GBS = 8000.0
+CUS = 256                 # MI355X compute units
+CLOCK_HZ = 2.4e9          # peak engine clock
 BOMP_ITERS = 3
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "gh_sweep_columns_paper_scale_hbm_traffic.md")
 SWEEP_SOURCES = [os.path.join(ROOT, "paper_2307_16550_amd", "csrc", f) for f in ("sweep_fast.hip", "sweep_table.h")]
@@ -58,9 +60,11 @@ BATCH_REPLAYS = 10
 EAGER_ROW_STEPS = 20
 
 
-def recorded_traffic():
-    """HBM bytes per sweep launch from the committed counter record, or None when
-    the sweep sources have changed since the counters were taken."""
+def recorded_traffic(key="traffic_bytes_per_launch"):
+    """A per-launch figure of the bilinear sweep from the committed counter record
+    (HBM bytes by default; "valu_insts_per_launch" for the VALU wave
+    instructions), or None when the sweep sources have changed since the
+    counters were taken."""
     import hashlib
     import re
     try:
@@ -73,7 +77,7 @@ def recorded_traffic():
         h.update(header[:header.index(DEVICE_PART_END)].encode())
     except (OSError, ValueError):
         return None
-    m_bytes = re.search(r"^traffic_bytes_per_launch:\s*(\d+)", text, re.M)
+    m_bytes = re.search(r"^" + key + r":\s*(\d+)", text, re.M)
     m_sha = re.search(r"^sweep_source_sha256:\s*([0-9a-f]{64})", text, re.M)
     if not m_bytes or not m_sha or m_sha.group(1) != h.hexdigest():
         return None
@@ -487,10 +491,16 @@ def main():
         "rd_maps_gbs": (y.numel() * 8 + radar.k * radar.nr * radar.nd * 8) / t_maps / 1e9,
         "roofline": {"kernel": "gh_sweep_columns<bilinear>" if interp == gh.BILINEAR else "gh_sweep_columns<bicubic>",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": recorded_traffic() if interp == gh.BILINEAR else None,
                      "algorithmic_bytes_per_launch": sweep_bytes,
                      "avg_launch_us": t_sweep * 1e6},
     }
+    # The sweep is limited by VALU issue and LDS, not HBM: the share of the
+    # launch's CU-cycles (one VALU wave instruction per CU per cycle) that the
+    # recorded VALU instruction count needs at the live launch time.
+    valu = recorded_traffic("valu_insts_per_launch") if interp == gh.BILINEAR else None
+    line["roofline"]["valu_issue_frac"] = (valu / CUS / (t_sweep * CLOCK_HZ)) if valu else None
 
     if not args.step_only:
         x = side_measurements()
