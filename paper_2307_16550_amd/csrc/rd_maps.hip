@@ -32,11 +32,11 @@ constexpr int kThreads = 512;
 constexpr int kBuf = 4096;        // complex values of FFT work per workgroup
 constexpr int kBfly = kBuf / 2 / kThreads;   // butterflies per thread and stage, at most
 
-// exp(-j pi num / den) with the numerator reduced exactly modulo 2 den.
+// exp(-j pi num / den) with the numerator reduced exactly modulo 2 den; den is
+// a power of two (every transform length here is), so the reduction is a mask
+// (two's complement gives the non-negative residue for negative num too).
 __device__ __forceinline__ float2 expm_pi(long long num, int den) {
-    const long long two = 2LL * den;
-    long long r = num % two;
-    if (r < 0) r += two;
+    const long long r = num & (2LL * den - 1);
     float s, c;
     sincospif((float)r / (float)den, &s, &c);
     return make_float2(c, -s);
