@@ -3,8 +3,8 @@
 
 One step is one synthetic frame of the paper-scale workload (4 receivers,
 Ms = 256 samples x Mc = 128 chirps, complex64, 3 targets, SNR 10 dB, f0 = 24 GHz,
-B = 250 MHz, Tc = 256 us) through every row of the hot path, all enqueued on
-one stream with no host synchronisation inside the step:
+B = 250 MHz, Tc = 256 us) through every row of the hot path, with no host
+synchronisation inside the step:
   1. range-Doppler maps (zero padding x4): 4 maps of 1024 x 512 bins;
   2. grid-hopping decision, bilinear, on the 128 x 128 x 32 x 32 grid
      (16,777,216 points), FP32 volume written, block maxima, global argmax;
@@ -16,10 +16,15 @@ one stream with no host synchronisation inside the step:
 Grid points evaluated per step: 4 x 16,777,216 (grid hopping) + 1,048,576
 (direct).  `value` is that count divided by the measured step time.  The
 step is captured once in a HIP graph (kernel launches and one device copy;
-no memset) and the timed steps are graph replays; the per-row times come
-from eager steps with HIP events, and after the replays the step's outputs
-(argmax cells, Block-OMP support and coefficients, refined estimates) are
-compared with those of an eager step (`graph_matches_eager`).
+no memset) and the timed steps are graph replays.  Rows 1-2, row 3 and rows
+4-5 are three independent chains: by default (`--streams 2`) rows 3 and then
+1-2 are captured on a second stream, forked from and joined back into the
+capture stream, so they run beside Block-OMP and the refinement;
+`--streams 1` captures everything on one stream in the order above.  The
+per-row times come from eager one-stream steps with HIP events, and after
+the replays the step's outputs (argmax cells, Block-OMP support and
+coefficients, refined estimates) are compared with those of an eager step
+(`graph_matches_eager`).
 
 The roofline object covers the dominant kernel, the grid-hopping sweep of
 step 2, timed with HIP events on the stream it runs on; its algorithmic bytes
@@ -89,6 +94,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--streams", type=int, choices=(1, 2), default=2,
+                    help="streams of the captured step: 2 runs the independent rows beside Block-OMP")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batching-workload measurement")
     ap.add_argument("--step-only", action="store_true",
@@ -371,10 +378,38 @@ def main():
     snap = lambda: [t.clone() for t in (arg, darg, bomp.support, bomp.alpha, theta)]
     ref = snap()
 
+    # The rows form three independent chains: (A) maps, sweep, argmax; (B) the
+    # direct decision and its argmax; (C) Block-OMP and the refinement, which
+    # rebuild their own maps from their own residual.  With two streams, B then
+    # A run on a second stream (default priority), forked from and joined back
+    # into the capture stream, beside C.
+    side = torch.cuda.Stream(device=dev) if args.streams == 2 else None
+
+    def step_two_streams():
+        main_s = torch.cuda.current_stream()
+        fork, join = torch.cuda.Event(), torch.cuda.Event()
+        fork.record(main_s)
+        side.wait_event(fork)
+        with torch.cuda.stream(side):
+            gh.direct_decision(radar, dgrid, y, ws=ws, dec=ddec, block=dblock, want_argmax=False)
+            gh.argmax(dblock, darg)
+            gh.rd_maps(radar, y, maps)
+            gh.decision(radar, grid, maps, interp, dec=dec, block=block, want_argmax=False)
+            gh.argmax(block, arg)
+        bomp.reset()
+        for _ in range(BOMP_ITERS):
+            bomp.step()
+        gh.refine(radar, grid, y, bomp.support, theta=theta, ws=rws)
+        join.record(side)
+        main_s.wait_event(join)
+
     # the timed steps: the whole step captured once in a HIP graph and replayed
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        step(False)
+        if side is not None:
+            step_two_streams()
+        else:
+            step(False)
     for _ in range(args.warmup):
         graph.replay()
     torch.cuda.synchronize()
@@ -481,6 +516,7 @@ def main():
             "interp": args.interp,
         },
         "step_launch": "hip_graph",
+        "step_streams": args.streams,
         "graph_matches_eager": graph_matches_eager,
         "rows_ms": {"rd_maps": t_maps * 1e3, "gh_sweep": t_sweep * 1e3, "argmax": t_arg * 1e3,
                     "direct": t_dir * 1e3, "bomp_refine_rest": (t_total - t_maps - t_sweep - t_arg - t_dir) * 1e3},

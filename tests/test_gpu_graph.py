@@ -2,6 +2,9 @@
 decision and argmax, three Block-OMP steps, refinement) captured once in a HIP
 graph: three replays on new frames, copied into the captured input buffer
 between replays, each equal bit for bit to an eager step on the same frame.
+The step is captured on one stream, and on two: the direct decision and then
+the grid-hopping row on a second stream (default priority), forked from and
+joined back into the capture stream, beside Block-OMP and the refinement.
 The eager path itself is checked against the FP64 oracle in test_gpu_parity.py.
 """
 import numpy as np
@@ -14,8 +17,9 @@ from paper_2307_16550_amd import scene as sc
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("streams", [1, 2])
 @pytest.mark.parametrize("cfg", [1, 2])
-def test_step_graph_replays_match_eager(cfg):
+def test_step_graph_replays_match_eager(cfg, streams):
     dev = torch.device("cuda:0")
     s = sc.make_scene(cfg, 0)
     radar = gh.Radar.from_scene(s)
@@ -46,6 +50,26 @@ def test_step_graph_replays_match_eager(cfg):
             bomp.step()
         gh.refine(radar, grid, y, bomp.support, theta=theta, ws=rws)
 
+    side = torch.cuda.Stream(device=dev)
+
+    def step_two_streams():
+        main_s = torch.cuda.current_stream()
+        fork, join = torch.cuda.Event(), torch.cuda.Event()
+        fork.record(main_s)
+        side.wait_event(fork)
+        with torch.cuda.stream(side):
+            gh.direct_decision(radar, dgrid, y, ws=ws, dec=ddec, block=dblock, want_argmax=False)
+            gh.argmax(dblock, darg)
+            gh.rd_maps(radar, y, maps)
+            gh.decision(radar, grid, maps, gh.BILINEAR, dec=dec, block=block, want_argmax=False)
+            gh.argmax(block, arg)
+        bomp.reset()
+        for _ in range(3):
+            bomp.step()
+        gh.refine(radar, grid, y, bomp.support, theta=theta, ws=rws)
+        join.record(side)
+        main_s.wait_event(join)
+
     def outputs():
         return [t.clone() for t in (maps, dec, arg, ddec, darg, bomp.support, bomp.alpha, bomp.resid, theta)]
 
@@ -53,7 +77,10 @@ def test_step_graph_replays_match_eager(cfg):
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        step()
+        if streams == 2:
+            step_two_streams()
+        else:
+            step()
     for rep in range(3):
         s2 = sc.make_scene(cfg, 10 + rep)
         y.copy_(torch.from_numpy(s2.y).to(dev))
@@ -67,4 +94,4 @@ def test_step_graph_replays_match_eager(cfg):
         names = ("maps", "dec", "arg", "ddec", "darg", "support", "alpha", "resid", "theta")
         for n, a, b in zip(names, got, want):
             assert torch.equal(a, b), f"replay {rep}: {n} differs from the eager step"
-        print(f"cfg {cfg} replay {rep}: support {bomp.support.cpu().numpy()}", flush=True)
+        print(f"cfg {cfg} streams {streams} replay {rep}: support {bomp.support.cpu().numpy()}", flush=True)
