@@ -397,8 +397,16 @@ def main():
             gh.decision(radar, grid, maps, interp, dec=dec, block=block, want_argmax=False)
             gh.argmax(block, arg)
         bomp.reset()
-        for _ in range(BOMP_ITERS):
+        for _ in range(BOMP_ITERS - 1):
             bomp.step()
+        # the refinement needs only the selections: the last fit runs on the
+        # second stream, beside it
+        bomp.select()
+        selected = torch.cuda.Event()
+        selected.record(main_s)
+        side.wait_event(selected)
+        with torch.cuda.stream(side):
+            bomp.fit()
         gh.refine(radar, grid, y, bomp.support, theta=theta, ws=rws)
         join.record(side)
         main_s.wait_event(join)

@@ -174,8 +174,9 @@ size_t gh_bomp_workspace_bytes(const gh_radar *radar, const gh_grid *grid, int32
 
 /* One Block-OMP iteration (multi-target extension the paper names as future
  * work, Sec. VI):
- *   1. decision on the residual d_resid (grid hopping on gh_rd_maps(d_resid),
- *      written to d_maps, if use_direct == 0; else the direct decision);
+ *   1. decision on the residual (grid hopping on gh_rd_maps of it, written to
+ *      d_maps, if use_direct == 0; else the direct decision); the residual is
+ *      d_resid, or d_y itself when n_support == 0 (d_resid is then not read);
  *   2. select the maximum over the grid excluding the n_support cells already
  *      in d_support; store its index at d_support[n_support];
  *   3. for each receiver, least squares over the n_support + 1 selected cells
@@ -183,16 +184,36 @@ size_t gh_bomp_workspace_bytes(const gh_radar *radar, const gh_grid *grid, int32
  *      normal equations in FP64 with the Gram matrix in closed form;
  *      alpha (complex64 [n_support+1][K], row t = cell d_support[t]) to d_alpha;
  *   4. d_resid <- Y - sum_t alpha_t A(theta_t) (FP32).
- * d_y: original frames (read).  d_resid: complex64 [K][Mc][Ms], in/out (the
- * caller starts with a copy of d_y).  d_maps: complex64 map buffer (written
- * when use_direct == 0; may be NULL otherwise).  d_support: int64
- * [max_support], in/out.  0 <= n_support < max_support <= GH_MAX_SUPPORT.
- * d_selected: gh_peak [1] (NULL: not written), the selected maximum.
- * Everything stays on the device; no host synchronisation inside. */
+ * d_y: original frames (read).  d_resid: complex64 [K][Mc][Ms], in/out.
+ * d_maps: complex64 map buffer (written when use_direct == 0; may be NULL
+ * otherwise).  d_support: int64 [max_support], in/out.
+ * 0 <= n_support < max_support <= GH_MAX_SUPPORT.  d_selected: gh_peak [1]
+ * (NULL: not written), the selected maximum.  Everything stays on the
+ * device; no host synchronisation inside.  The same as gh_bomp_select
+ * followed by gh_bomp_fit with n_selected = n_support + 1. */
 int gh_bomp_step(const gh_radar *radar, const gh_grid *grid, const void *d_y, void *d_resid, void *d_maps,
                  int32_t use_direct, int32_t interp, int32_t gemm_dtype, int64_t *d_support,
                  int32_t n_support, int32_t max_support, void *d_alpha, gh_peak *d_selected,
                  void *d_ws, size_t ws_bytes, void *stream);
+
+/* Steps 1 and 2 of gh_bomp_step alone (arguments as there): after it,
+ * d_support[0 .. n_support] holds the selection.  Lets a caller start work
+ * that needs only the selected cells (gh_refine) before the fit. */
+int gh_bomp_select(const gh_radar *radar, const gh_grid *grid, const void *d_y, const void *d_resid,
+                   void *d_maps, int32_t use_direct, int32_t interp, int32_t gemm_dtype, int64_t *d_support,
+                   int32_t n_support, int32_t max_support, gh_peak *d_selected, void *d_ws, size_t ws_bytes,
+                   void *stream);
+
+/* Steps 3 and 4 of gh_bomp_step alone: least squares over the n_selected
+ * cells d_support[0 .. n_selected) (1 <= n_selected <= max_support <=
+ * GH_MAX_SUPPORT), alpha (complex64 [n_selected][K]) to d_alpha, and
+ * d_resid <- Y - sum_t alpha_t A(theta_t).  d_ws: a workspace of
+ * gh_bomp_workspace_bytes(radar, grid, use_direct, gemm_dtype) bytes for any
+ * use_direct and gemm_dtype (this call uses the part they share); it must not
+ * be in use by a gh_bomp_select or gh_bomp_step still running on another
+ * stream. */
+int gh_bomp_fit(const gh_radar *radar, const gh_grid *grid, const void *d_y, void *d_resid, const int64_t *d_support,
+                int32_t n_selected, int32_t max_support, void *d_alpha, void *d_ws, size_t ws_bytes, void *stream);
 
 /* Workspace of gh_refine in bytes for n_cells (1..65535) starting cells; 0 on
  * invalid arguments (see gh_last_error). */

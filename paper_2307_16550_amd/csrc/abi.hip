@@ -290,46 +290,119 @@ size_t gh_bomp_workspace_bytes(const gh_radar* radar, const gh_grid* grid, int32
     return b;
 }
 
+// Shared checks of the Block-OMP entry points; sets g, gp.
+static int bomp_common(const gh_radar* radar, const gh_grid* grid, int32_t use_direct, int32_t interp,
+                       int32_t gemm_dtype, int32_t max_support, gh::Geom& g, gh::GridP& gp) {
+    int rc = make_geom(radar, g);
+    if (rc || (rc = make_grid(grid, gp)) || (rc = check_gemm(gemm_dtype))) return rc;
+    if (use_direct != 0 && use_direct != 1) return fail(GH_EINVAL, "use_direct must be 0 or 1");
+    if (!use_direct && (rc = check_sweep_limits(g, interp))) return rc;
+    if (max_support < 1 || max_support > GH_MAX_SUPPORT)
+        return fail(GH_EINVAL, "max_support must be in [1, %d]", GH_MAX_SUPPORT);
+    return GH_OK;
+}
+
+// Decision on the residual (y itself at n_support == 0) and selection into
+// support[n_support].  Arguments already checked.
+static hipError_t bomp_select_launch(const gh::Geom& g, const gh::GridP& gp, const void* d_y, const void* d_resid,
+                                     void* d_maps, int32_t use_direct, int32_t interp, int32_t gemm_dtype,
+                                     int64_t* d_support, int32_t n_support, gh_peak* d_selected, char* ws,
+                                     hipStream_t st) {
+    const float2* src = (const float2*)(n_support == 0 ? d_y : d_resid);
+    gh_peak* block = (gh_peak*)ws;
+    ws += align256((size_t)gp.nloc * sizeof(gh_peak));
+    ws += align256(gh::bomp_fit_ws_bytes(g));
+    hipError_t e;
+    if (use_direct) {
+        e = gh::launch_direct(g, gp, src, gemm_dtype, ws, nullptr, block, d_support, n_support, st);
+    } else {
+        e = gh::launch_rd_maps(g, src, d_maps, GH_MAP_C64, st);
+        if (e == hipSuccess)
+            e = gh::launch_gh_sweep(g, gp, d_maps, GH_MAP_C64, interp, nullptr, block, d_support, n_support, st);
+    }
+    if (e == hipSuccess) e = gh::launch_peak_final(block, gp.nloc, d_selected, d_support + n_support, st);
+    return e;
+}
+
+static hipError_t bomp_fit_launch(const gh::Geom& g, const gh::GridP& gp, const void* d_y, void* d_resid,
+                                  const int64_t* d_support, int32_t n_selected, void* d_alpha, char* ws,
+                                  hipStream_t st) {
+    void* fit_ws = ws + align256((size_t)gp.nloc * sizeof(gh_peak));
+    return gh::launch_bomp_fit(g, gp, (const float2*)d_y, (float2*)d_resid, d_support, n_selected,
+                               (float2*)d_alpha, fit_ws, st);
+}
+
+static int bomp_select_checks(const gh::GridP& gp, const void* d_y, const void* d_resid, const void* d_maps,
+                              int32_t use_direct, const int64_t* d_support, int32_t n_support, int32_t max_support,
+                              const gh_peak* d_selected, const void* d_ws) {
+    if (!d_y || !d_support || !d_ws || (n_support > 0 && !d_resid)) return fail(GH_EINVAL, "NULL device pointer");
+    if (!use_direct && !d_maps) return fail(GH_EINVAL, "d_maps must be non-NULL for grid hopping");
+    if (int rc = check_aligned({d_y, d_resid, d_maps, d_support, d_selected, d_ws})) return rc;
+    if (n_support < 0 || n_support >= max_support)
+        return fail(GH_EINVAL, "n_support = %d must be in [0, max_support)", n_support);
+    if (n_support + 1 > gp.nloc * (long long)gp.nv) return fail(GH_EINVAL, "support larger than the grid");
+    return GH_OK;
+}
+
 int gh_bomp_step(const gh_radar* radar, const gh_grid* grid, const void* d_y, void* d_resid, void* d_maps,
                  int32_t use_direct, int32_t interp, int32_t gemm_dtype, int64_t* d_support, int32_t n_support,
                  int32_t max_support, void* d_alpha, gh_peak* d_selected, void* d_ws, size_t ws_bytes, void* stream) {
     gh::Geom g;
     gh::GridP gp;
-    int rc = make_geom(radar, g);
-    if (rc || (rc = make_grid(grid, gp)) || (rc = check_gemm(gemm_dtype))) return rc;
-    if (use_direct != 0 && use_direct != 1) return fail(GH_EINVAL, "use_direct must be 0 or 1");
-    if (!use_direct && (rc = check_sweep_limits(g, interp))) return rc;
-    if (!d_y || !d_resid || !d_support || !d_alpha || !d_ws) return fail(GH_EINVAL, "NULL device pointer");
-    if (!use_direct && !d_maps) return fail(GH_EINVAL, "d_maps must be non-NULL for grid hopping");
-    if ((rc = check_aligned({d_y, d_resid, d_maps, d_support, d_alpha, d_selected, d_ws}))) return rc;
-    if (max_support < 1 || max_support > GH_MAX_SUPPORT)
-        return fail(GH_EINVAL, "max_support must be in [1, %d]", GH_MAX_SUPPORT);
-    if (n_support < 0 || n_support >= max_support)
-        return fail(GH_EINVAL, "n_support = %d must be in [0, max_support)", n_support);
-    if (n_support + 1 > gp.nloc * (long long)gp.nv) return fail(GH_EINVAL, "support larger than the grid");
+    int rc = bomp_common(radar, grid, use_direct, interp, gemm_dtype, max_support, g, gp);
+    if (rc) return rc;
+    if (!d_resid || !d_alpha) return fail(GH_EINVAL, "NULL device pointer");
+    if ((rc = bomp_select_checks(gp, d_y, d_resid, d_maps, use_direct, d_support, n_support, max_support, d_selected,
+                                 d_ws)) ||
+        (rc = check_aligned({d_alpha})))
+        return rc;
     const size_t need = gh_bomp_workspace_bytes(radar, grid, use_direct, gemm_dtype);
     if (ws_bytes < need) return fail(GH_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if ((rc = check_device())) return rc;
     hipStream_t st = (hipStream_t)stream;
-    char* ws = (char*)d_ws;
-    gh_peak* block = (gh_peak*)ws;
-    ws += align256((size_t)gp.nloc * sizeof(gh_peak));
-    void* fit_ws = ws;
-    ws += align256(gh::bomp_fit_ws_bytes(g));
-    void* dir_ws = ws;
-    hipError_t e;
-    if (use_direct) {
-        e = gh::launch_direct(g, gp, (const float2*)d_resid, gemm_dtype, dir_ws, nullptr, block, d_support, n_support, st);
-    } else {
-        e = gh::launch_rd_maps(g, (const float2*)d_resid, d_maps, GH_MAP_C64, st);
-        if (e == hipSuccess)
-            e = gh::launch_gh_sweep(g, gp, d_maps, GH_MAP_C64, interp, nullptr, block, d_support, n_support, st);
-    }
-    if (e == hipSuccess) e = gh::launch_peak_final(block, gp.nloc, d_selected, d_support + n_support, st);
-    if (e == hipSuccess)
-        e = gh::launch_bomp_fit(g, gp, (const float2*)d_y, (float2*)d_resid, d_support, n_support + 1,
-                                (float2*)d_alpha, fit_ws, st);
+    hipError_t e = bomp_select_launch(g, gp, d_y, d_resid, d_maps, use_direct, interp, gemm_dtype, d_support,
+                                      n_support, d_selected, (char*)d_ws, st);
+    if (e == hipSuccess) e = bomp_fit_launch(g, gp, d_y, d_resid, d_support, n_support + 1, d_alpha, (char*)d_ws, st);
     if (e != hipSuccess) return hip_fail(e, "gh_bomp_step launch");
+    return ok();
+}
+
+int gh_bomp_select(const gh_radar* radar, const gh_grid* grid, const void* d_y, const void* d_resid, void* d_maps,
+                   int32_t use_direct, int32_t interp, int32_t gemm_dtype, int64_t* d_support, int32_t n_support,
+                   int32_t max_support, gh_peak* d_selected, void* d_ws, size_t ws_bytes, void* stream) {
+    gh::Geom g;
+    gh::GridP gp;
+    int rc = bomp_common(radar, grid, use_direct, interp, gemm_dtype, max_support, g, gp);
+    if (rc) return rc;
+    if ((rc = bomp_select_checks(gp, d_y, d_resid, d_maps, use_direct, d_support, n_support, max_support, d_selected,
+                                 d_ws)))
+        return rc;
+    const size_t need = gh_bomp_workspace_bytes(radar, grid, use_direct, gemm_dtype);
+    if (ws_bytes < need) return fail(GH_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if ((rc = check_device())) return rc;
+    const hipError_t e = bomp_select_launch(g, gp, d_y, d_resid, d_maps, use_direct, interp, gemm_dtype, d_support,
+                                            n_support, d_selected, (char*)d_ws, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gh_bomp_select launch");
+    return ok();
+}
+
+int gh_bomp_fit(const gh_radar* radar, const gh_grid* grid, const void* d_y, void* d_resid, const int64_t* d_support,
+                int32_t n_selected, int32_t max_support, void* d_alpha, void* d_ws, size_t ws_bytes, void* stream) {
+    gh::Geom g;
+    gh::GridP gp;
+    int rc = bomp_common(radar, grid, 0, GH_INTERP_BILINEAR, GH_GEMM_F32, max_support, g, gp);
+    if (rc) return rc;
+    if (!d_y || !d_resid || !d_support || !d_alpha || !d_ws) return fail(GH_EINVAL, "NULL device pointer");
+    if ((rc = check_aligned({d_y, d_resid, d_support, d_alpha, d_ws}))) return rc;
+    if (n_selected < 1 || n_selected > max_support)
+        return fail(GH_EINVAL, "n_selected = %d must be in [1, max_support]", n_selected);
+    if (n_selected > gp.nloc * (long long)gp.nv) return fail(GH_EINVAL, "support larger than the grid");
+    const size_t need = gh_bomp_workspace_bytes(radar, grid, 0, GH_GEMM_F32);
+    if (ws_bytes < need) return fail(GH_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if ((rc = check_device())) return rc;
+    const hipError_t e = bomp_fit_launch(g, gp, d_y, d_resid, d_support, n_selected, d_alpha, (char*)d_ws,
+                                         (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gh_bomp_fit launch");
     return ok();
 }
 

@@ -25,7 +25,8 @@ MAP_C64, MAP_F16, MAP_BF16 = 0, 1, 2
 MAX_SUPPORT = 32
 
 EXPORTS = ("gh_abi_version", "gh_last_error", "gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_workspace_bytes",
-           "gh_direct_decision", "gh_bomp_workspace_bytes", "gh_bomp_step", "gh_refine_workspace_bytes",
+           "gh_direct_decision", "gh_bomp_workspace_bytes", "gh_bomp_step", "gh_bomp_select", "gh_bomp_fit",
+           "gh_refine_workspace_bytes",
            "gh_refine", "gh_direct_points_workspace_bytes", "gh_direct_points", "gh_gh_points",
            "gh_range_spectra", "gh_factored_workspace_bytes", "gh_factored_decision",
            "gh_batch_workspace_bytes", "gh_batch_create", "gh_batch_tune", "gh_batch_get_info", "gh_batch_run",
@@ -89,6 +90,8 @@ def load():
     lib.gh_bomp_workspace_bytes.argtypes = [rp, gp_, i32, i32]
     lib.gh_bomp_workspace_bytes.restype = sz
     lib.gh_bomp_step.argtypes = [rp, gp_, vp, vp, vp, i32, i32, i32, vp, i32, i32, vp, pp, vp, sz, vp]
+    lib.gh_bomp_select.argtypes = [rp, gp_, vp, vp, vp, i32, i32, i32, vp, i32, i32, pp, vp, sz, vp]
+    lib.gh_bomp_fit.argtypes = [rp, gp_, vp, vp, vp, i32, i32, vp, vp, sz, vp]
     lib.gh_refine_workspace_bytes.argtypes = [rp, gp_, i32]
     lib.gh_refine_workspace_bytes.restype = sz
     lib.gh_refine.argtypes = [rp, gp_, vp, vp, i32, i32, vp, sz, vp, vp]
@@ -110,7 +113,8 @@ def load():
     lib.gh_batch_frame_maps.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_void_p)]
     lib.gh_batch_destroy.argtypes = [vp]
     lib.gh_batch_destroy.restype = None
-    for name in ("gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_decision", "gh_bomp_step", "gh_refine",
+    for name in ("gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_decision", "gh_bomp_step", "gh_bomp_select",
+                 "gh_bomp_fit", "gh_refine",
                  "gh_direct_points", "gh_gh_points", "gh_range_spectra", "gh_factored_decision", "gh_batch_create", "gh_batch_tune", "gh_batch_get_info",
                  "gh_batch_run", "gh_batch_frame_maps"):
         getattr(lib, name).restype = ctypes.c_int
@@ -296,17 +300,44 @@ class BompState:
         self.selected = peaks_tensor(1, dev)
         self.ws = torch.empty(bomp_workspace_bytes(radar, grid, use_direct, gemm), dtype=torch.uint8, device=dev)
         self.n = 0
+        self._selected_pending = False
 
     def reset(self):
-        self.resid.copy_(self.y)
+        """Start over: the next step selects on y itself (the residual is not read then)."""
         self.n = 0
+        self._selected_pending = False
 
     def step(self, stream=None):
+        if self._selected_pending:
+            raise RuntimeError("select() was called without fit()")
         lib = load()
         _check(lib.gh_bomp_step(ctypes.byref(self.radar.c_struct), ctypes.byref(self.grid), _ptr(self.y),
                                 _ptr(self.resid), _ptr(self.maps), self.use_direct, self.interp, self.gemm,
                                 _ptr(self.support), self.n, self.max_support, _ptr(self.alpha), _ptr(self.selected),
                                 _ptr(self.ws), self.ws.numel(), _stream(stream)))
+        self.n += 1
+
+    def select(self, stream=None):
+        """First half of step(): the decision on the residual and the new selection
+        (support[n]); fit() completes the iteration."""
+        if self._selected_pending:
+            raise RuntimeError("select() called twice without fit()")
+        lib = load()
+        _check(lib.gh_bomp_select(ctypes.byref(self.radar.c_struct), ctypes.byref(self.grid), _ptr(self.y),
+                                  _ptr(self.resid), _ptr(self.maps), self.use_direct, self.interp, self.gemm,
+                                  _ptr(self.support), self.n, self.max_support, _ptr(self.selected),
+                                  _ptr(self.ws), self.ws.numel(), _stream(stream)))
+        self._selected_pending = True
+
+    def fit(self, stream=None):
+        """Second half of step(): least squares over the n + 1 selected cells and the residual."""
+        if not self._selected_pending:
+            raise RuntimeError("fit() needs a select() first")
+        lib = load()
+        _check(lib.gh_bomp_fit(ctypes.byref(self.radar.c_struct), ctypes.byref(self.grid), _ptr(self.y),
+                               _ptr(self.resid), _ptr(self.support), self.n + 1, self.max_support, _ptr(self.alpha),
+                               _ptr(self.ws), self.ws.numel(), _stream(stream)))
+        self._selected_pending = False
         self.n += 1
 
 

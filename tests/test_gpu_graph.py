@@ -64,8 +64,14 @@ def test_step_graph_replays_match_eager(cfg, streams):
             gh.decision(radar, grid, maps, gh.BILINEAR, dec=dec, block=block, want_argmax=False)
             gh.argmax(block, arg)
         bomp.reset()
-        for _ in range(3):
+        for _ in range(2):
             bomp.step()
+        bomp.select()
+        selected = torch.cuda.Event()
+        selected.record(main_s)
+        side.wait_event(selected)
+        with torch.cuda.stream(side):
+            bomp.fit()
         gh.refine(radar, grid, y, bomp.support, theta=theta, ws=rws)
         join.record(side)
         main_s.wait_event(join)

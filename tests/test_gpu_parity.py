@@ -335,6 +335,32 @@ def test_bomp_fit_cfg2_full_size():
     assert np.linalg.norm(st.resid.cpu().numpy() - resid_ref) <= 1e-5 * np.linalg.norm(s.y.astype(np.complex128))
 
 
+@pytest.mark.parametrize("use_direct", [False, True])
+def test_bomp_select_then_fit_equals_step(use_direct):
+    """gh_bomp_select + gh_bomp_fit give what gh_bomp_step gives, bit for bit, and a
+    reset run (the stale residual is not read at the first selection) repeats the first."""
+    say(f"bomp select/fit use_direct={use_direct}")
+    s, r, gr = scene_and_radar(1, 0)
+    grid = gh.grid_of(s.grid)
+    y = to_dev(s.y)
+    a = gh.BompState(gr, grid, y, max_support=3, use_direct=use_direct)
+    b = gh.BompState(gr, grid, y, max_support=3, use_direct=use_direct)
+    for _ in range(3):
+        a.step()
+        b.select()
+        b.fit()
+    torch.cuda.synchronize()
+    first = [t.clone() for t in (a.support, a.alpha, a.resid)]
+    for name, u, v in zip(("support", "alpha", "resid"), first, (b.support, b.alpha, b.resid)):
+        assert torch.equal(u, v), name
+    a.reset()
+    for _ in range(3):
+        a.step()
+    torch.cuda.synchronize()
+    for name, u, v in zip(("support", "alpha", "resid"), first, (a.support, a.alpha, a.resid)):
+        assert torch.equal(u, v), f"after reset: {name}"
+
+
 # ---------------------------------------------------------------- refinement
 
 @pytest.mark.parametrize("kernel", ["cluster", "single"])
