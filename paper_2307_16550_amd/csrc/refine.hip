@@ -551,6 +551,22 @@ __global__ __launch_bounds__(kThreads) void refine_single_kernel(Geom g, GridP g
 // together; each barrier wait is bounded regardless (an expired wait aborts the
 // launch's cells, whose estimates are then NaN).
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// C += A B for one 16 x 16 complex tile on the matrix cores (FP32, four real
+// 16x16x4 products per complex one).  Lane l = r + 16 g holds the contraction
+// indices 8 g + e (e < 8) of row r of A and of column r of B; the output
+// element (i, j) is in lane j + 16 (i / 4), slot i % 4.
+__device__ __forceinline__ void mfma_tile(const float2 (&a)[8], const float2 (&b)[8], f32x4& cre, f32x4& cim) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e].x, b[e].x, cre, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[e].y, b[e].y, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e].x, b[e].y, cim, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e].y, b[e].x, cim, 0, 0, 0);
+    }
+}
+
 constexpr int kCT = 512;             // threads of a cluster workgroup
 constexpr int kCand = 8;             // points per pass
 constexpr int kRowsMaxC = kCT / kCand;   // rows per workgroup (one thread per (point, row))
@@ -612,6 +628,15 @@ struct ClusterCtx {
     int cell, part, slot0, r0, nrows, q_lo, nq;
 };
 
+// The matrix-core per-row sums apply when every row of a workgroup belongs to
+// one receiver, the rows form 16-row tiles and the samples 32- or 64-sample steps.
+__device__ __forceinline__ bool mfma_rows(const Cluster& cl, int ms, const ClusterCtx& cx) {
+    const int R = cl.rows_per_wg;
+    const int ntiles = (R >> 4) * 2;
+    const int kparts = ntiles >= kCT / 64 ? 1 : 2;
+    return cx.nq == 1 && R % 16 == 0 && ntiles * kparts <= kCT / 64 && ms % (32 * kparts) == 0;
+}
+
 // One pass at the points sh.th[0 .. npts): leaves all six moments of every
 // receiver at each point in sh.mom.  er: LDS table of range phase factors.
 __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx& cx, const float2* __restrict__ y,
@@ -639,8 +664,62 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
         sh.ed[c][r] = expm_fixed(sh.fd[c][(gr >> g.log2_mc) - cx.q_lo] * (uint32_t)(gr & (mc - 1)));
     }
     __syncthreads();
-    // per row and point: A_p = sum_s s^p Y[row][s] e_r[s] (FP32 products and sums, tpr lanes per row)
-    {
+    // per row and point: A_p = sum_s s^p Y[row][s] e_r[s]
+    if (npts > 2 && mfma_rows(cl, ms, cx)) {
+        // On the matrix cores (passes of more than two points; one or two
+        // points take the VALU path below): C[row][col] = sum_s Y[row][s] B[s][col], col = 8 p + c,
+        // B[s][col] = s^p e_c[s] (columns 24..31 zero), as 16 x 16 complex tiles.
+        // The (R / 16) x 2 tiles go to waves t + ntiles h, h < kparts, each over
+        // its part of the samples; part 0 stores, part 1 then adds (fixed order).
+        const int wave = tid >> 6, lane = tid & 63;
+        const int r = lane & 15, grp = lane >> 4;
+        const int ntiles = (R >> 4) * 2;
+        const int kparts = ntiles >= kCT / 64 ? 1 : 2;
+        const int h = wave / ntiles, t = wave - h * ntiles;
+        const bool active = h < kparts;
+        f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+        if (active) {
+            const int row = (t >> 1) * 16 + r, col = (t & 1) * 16 + r;
+            const int pw = col >> 3, c = col & 7;
+            const bool rowv = row < cx.nrows, colv = col < 24 && c < npts;
+            const float2* yr = y + (size_t)(cx.r0 + (rowv ? row : 0)) * ms;
+            const float2* ec = er + c * ms;
+            const int span = ms / kparts;
+            for (int s0 = h * span; s0 < (h + 1) * span; s0 += 32) {
+                const int sb = s0 + grp * 8;
+                float2 a[8], b[8];
+                const float4* y4 = reinterpret_cast<const float4*>(yr + sb);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float4 v = rowv ? y4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    a[2 * i] = make_float2(v.x, v.y);
+                    a[2 * i + 1] = make_float2(v.z, v.w);
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float fs = (float)(sb + e);
+                    const float w = pw == 0 ? 1.f : (pw == 1 ? fs : fs * fs);
+                    const float2 ev = colv ? ec[sb + e] : make_float2(0.f, 0.f);
+                    b[e] = make_float2(ev.x * w, ev.y * w);
+                }
+                mfma_tile(a, b, cre, cim);
+            }
+        }
+        const int j = (t & 1) * 16 + r, c_out = j & 7, p_out = j >> 3;
+        if (active && h == 0 && j < 24) {
+#pragma unroll
+            for (int sl = 0; sl < 4; ++sl) sh.a[c_out][p_out][(t >> 1) * 16 + 4 * grp + sl] = make_float2(cre[sl], cim[sl]);
+        }
+        __syncthreads();
+        if (active && h == 1 && j < 24) {
+#pragma unroll
+            for (int sl = 0; sl < 4; ++sl) {
+                float2& d = sh.a[c_out][p_out][(t >> 1) * 16 + 4 * grp + sl];
+                d = make_float2(d.x + cre[sl], d.y + cim[sl]);
+            }
+        }
+    } else {
+        // on the VALU: FP32 products and sums, tpr lanes per row
         const int tpr = kCT / R;
         const int row = tid / tpr, lane = tid & (tpr - 1);
         float acc[kCand][6];
