@@ -17,10 +17,12 @@ Grid points evaluated per step: 4 x 16,777,216 (grid hopping) + 1,048,576
 (direct).  `value` is that count divided by the measured step time.  The
 step is captured once in a HIP graph (kernel launches and one device copy;
 no memset) and the timed steps are graph replays.  Rows 1-2, row 3 and rows
-4-5 are three independent chains: by default (`--streams 2`) rows 3 and then
-1-2 are captured on a second stream, forked from and joined back into the
-capture stream, so they run beside Block-OMP and the refinement;
-`--streams 1` captures everything on one stream in the order above.  The
+4-5 are three independent chains: by default (`--streams 2`) row 3 runs on a
+second stream beside the Block-OMP iterations, and rows 1-2 (after the last
+Block-OMP fit, which the refinement does not need) on that stream beside the
+refinement; the second stream is forked from and joined back into the
+capture stream.  `--streams 1` captures everything on one stream in the
+order above.  The
 per-row times come from eager one-stream steps with HIP events, and after
 the replays the step's outputs (argmax cells, Block-OMP support and
 coefficients, refined estimates) are compared with those of an eager step
@@ -380,9 +382,11 @@ def main():
 
     # The rows form three independent chains: (A) maps, sweep, argmax; (B) the
     # direct decision and its argmax; (C) Block-OMP and the refinement, which
-    # rebuild their own maps from their own residual.  With two streams, B then
-    # A run on a second stream (default priority), forked from and joined back
-    # into the capture stream, beside C.
+    # rebuild their own maps from their own residual.  With two streams, C runs
+    # on the capture stream; a second stream (default priority), forked from
+    # and joined back into it, runs B beside the Block-OMP iterations, then,
+    # once the last selection is made, the last fit (the refinement needs only
+    # the selections) and A beside the latency-bound refinement.
     side = torch.cuda.Stream(device=dev) if args.streams == 2 else None
 
     def step_two_streams():
@@ -393,20 +397,18 @@ def main():
         with torch.cuda.stream(side):
             gh.direct_decision(radar, dgrid, y, ws=ws, dec=ddec, block=dblock, want_argmax=False)
             gh.argmax(dblock, darg)
-            gh.rd_maps(radar, y, maps)
-            gh.decision(radar, grid, maps, interp, dec=dec, block=block, want_argmax=False)
-            gh.argmax(block, arg)
         bomp.reset()
         for _ in range(BOMP_ITERS - 1):
             bomp.step()
-        # the refinement needs only the selections: the last fit runs on the
-        # second stream, beside it
         bomp.select()
         selected = torch.cuda.Event()
         selected.record(main_s)
         side.wait_event(selected)
         with torch.cuda.stream(side):
             bomp.fit()
+            gh.rd_maps(radar, y, maps)
+            gh.decision(radar, grid, maps, interp, dec=dec, block=block, want_argmax=False)
+            gh.argmax(block, arg)
         gh.refine(radar, grid, y, bomp.support, theta=theta, ws=rws)
         join.record(side)
         main_s.wait_event(join)

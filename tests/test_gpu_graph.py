@@ -2,9 +2,10 @@
 decision and argmax, three Block-OMP steps, refinement) captured once in a HIP
 graph: three replays on new frames, copied into the captured input buffer
 between replays, each equal bit for bit to an eager step on the same frame.
-The step is captured on one stream, and on two: the direct decision and then
-the grid-hopping row on a second stream (default priority), forked from and
-joined back into the capture stream, beside Block-OMP and the refinement.
+The step is captured on one stream, and on two: a second stream (default
+priority), forked from and joined back into the capture stream, runs the
+direct decision beside the Block-OMP iterations, then the last Block-OMP fit
+and the grid-hopping row beside the refinement.
 The eager path itself is checked against the FP64 oracle in test_gpu_parity.py.
 """
 import numpy as np
@@ -60,9 +61,6 @@ def test_step_graph_replays_match_eager(cfg, streams):
         with torch.cuda.stream(side):
             gh.direct_decision(radar, dgrid, y, ws=ws, dec=ddec, block=dblock, want_argmax=False)
             gh.argmax(dblock, darg)
-            gh.rd_maps(radar, y, maps)
-            gh.decision(radar, grid, maps, gh.BILINEAR, dec=dec, block=block, want_argmax=False)
-            gh.argmax(block, arg)
         bomp.reset()
         for _ in range(2):
             bomp.step()
@@ -72,6 +70,9 @@ def test_step_graph_replays_match_eager(cfg, streams):
         side.wait_event(selected)
         with torch.cuda.stream(side):
             bomp.fit()
+            gh.rd_maps(radar, y, maps)
+            gh.decision(radar, grid, maps, gh.BILINEAR, dec=dec, block=block, want_argmax=False)
+            gh.argmax(block, arg)
         gh.refine(radar, grid, y, bomp.support, theta=theta, ws=rws)
         join.record(side)
         main_s.wait_event(join)
