@@ -286,7 +286,10 @@ size_t gh_bomp_workspace_bytes(const gh_radar* radar, const gh_grid* grid, int32
     if (make_geom(radar, g) || make_grid(grid, gp) || check_gemm(gemm_dtype)) return 0;
     ok();
     size_t b = align256((size_t)gp.nloc * sizeof(gh_peak)) + align256(gh::bomp_fit_ws_bytes(g));
-    if (use_direct) b += align256(gh::direct_ws_bytes(g, gp, gemm_dtype));
+    if (use_direct)
+        b += align256(gh::direct_ws_bytes(g, gp, gemm_dtype));
+    else
+        b += align256((size_t)g.k * g.nr * g.nd * sizeof(float2));   // maps of the residual
     return b;
 }
 
@@ -303,11 +306,15 @@ static int bomp_common(const gh_radar* radar, const gh_grid* grid, int32_t use_d
 }
 
 // Decision on the residual (y itself at n_support == 0) and selection into
-// support[n_support].  Arguments already checked.
+// support[n_support].  Grid hopping: the maps of y go to d_maps at
+// n_support == 0; later, the maps of the residual are built in the workspace
+// from them and the fitted atoms (closed form), or by the FFT of the residual
+// where the closed-form table does not fit (or GH_BOMP_MAPS=fft, diagnostics).
+// Arguments already checked.
 static hipError_t bomp_select_launch(const gh::Geom& g, const gh::GridP& gp, const void* d_y, const void* d_resid,
                                      void* d_maps, int32_t use_direct, int32_t interp, int32_t gemm_dtype,
-                                     int64_t* d_support, int32_t n_support, gh_peak* d_selected, char* ws,
-                                     hipStream_t st) {
+                                     int64_t* d_support, int32_t n_support, const void* d_alpha,
+                                     gh_peak* d_selected, char* ws, hipStream_t st) {
     const float2* src = (const float2*)(n_support == 0 ? d_y : d_resid);
     gh_peak* block = (gh_peak*)ws;
     ws += align256((size_t)gp.nloc * sizeof(gh_peak));
@@ -315,10 +322,21 @@ static hipError_t bomp_select_launch(const gh::Geom& g, const gh::GridP& gp, con
     hipError_t e;
     if (use_direct) {
         e = gh::launch_direct(g, gp, src, gemm_dtype, ws, nullptr, block, d_support, n_support, st);
-    } else {
+    } else if (n_support == 0) {
         e = gh::launch_rd_maps(g, src, d_maps, GH_MAP_C64, st);
         if (e == hipSuccess)
             e = gh::launch_gh_sweep(g, gp, d_maps, GH_MAP_C64, interp, nullptr, block, d_support, n_support, st);
+    } else {
+        const char* mode = getenv("GH_BOMP_MAPS");
+        const bool fft_only = mode && strcmp(mode, "fft") == 0;
+        float2* rmaps = (float2*)ws;
+        if (!fft_only && gh::bomp_resid_maps_ok(g, n_support))
+            e = gh::launch_bomp_resid_maps(g, gp, (const float2*)d_maps, d_support, n_support, (const float2*)d_alpha,
+                                           rmaps, st);
+        else
+            e = gh::launch_rd_maps(g, src, rmaps, GH_MAP_C64, st);
+        if (e == hipSuccess)
+            e = gh::launch_gh_sweep(g, gp, rmaps, GH_MAP_C64, interp, nullptr, block, d_support, n_support, st);
     }
     if (e == hipSuccess) e = gh::launch_peak_final(block, gp.nloc, d_selected, d_support + n_support, st);
     return e;
@@ -361,7 +379,7 @@ int gh_bomp_step(const gh_radar* radar, const gh_grid* grid, const void* d_y, vo
     if ((rc = check_device())) return rc;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = bomp_select_launch(g, gp, d_y, d_resid, d_maps, use_direct, interp, gemm_dtype, d_support,
-                                      n_support, d_selected, (char*)d_ws, st);
+                                      n_support, d_alpha, d_selected, (char*)d_ws, st);
     if (e == hipSuccess) e = bomp_fit_launch(g, gp, d_y, d_resid, d_support, n_support + 1, d_alpha, (char*)d_ws, st);
     if (e != hipSuccess) return hip_fail(e, "gh_bomp_step launch");
     return ok();
@@ -369,7 +387,8 @@ int gh_bomp_step(const gh_radar* radar, const gh_grid* grid, const void* d_y, vo
 
 int gh_bomp_select(const gh_radar* radar, const gh_grid* grid, const void* d_y, const void* d_resid, void* d_maps,
                    int32_t use_direct, int32_t interp, int32_t gemm_dtype, int64_t* d_support, int32_t n_support,
-                   int32_t max_support, gh_peak* d_selected, void* d_ws, size_t ws_bytes, void* stream) {
+                   int32_t max_support, const void* d_alpha, gh_peak* d_selected, void* d_ws, size_t ws_bytes,
+                   void* stream) {
     gh::Geom g;
     gh::GridP gp;
     int rc = bomp_common(radar, grid, use_direct, interp, gemm_dtype, max_support, g, gp);
@@ -377,11 +396,13 @@ int gh_bomp_select(const gh_radar* radar, const gh_grid* grid, const void* d_y, 
     if ((rc = bomp_select_checks(gp, d_y, d_resid, d_maps, use_direct, d_support, n_support, max_support, d_selected,
                                  d_ws)))
         return rc;
+    if (n_support > 0 && !d_alpha) return fail(GH_EINVAL, "NULL device pointer");
+    if ((rc = check_aligned({d_alpha}))) return rc;
     const size_t need = gh_bomp_workspace_bytes(radar, grid, use_direct, gemm_dtype);
     if (ws_bytes < need) return fail(GH_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if ((rc = check_device())) return rc;
     const hipError_t e = bomp_select_launch(g, gp, d_y, d_resid, d_maps, use_direct, interp, gemm_dtype, d_support,
-                                            n_support, d_selected, (char*)d_ws, (hipStream_t)stream);
+                                            n_support, d_alpha, d_selected, (char*)d_ws, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gh_bomp_select launch");
     return ok();
 }

@@ -225,7 +225,76 @@ __global__ __launch_bounds__(kThreads) void bomp_fit_residual_kernel(Geom g, Gri
     }
 }
 
+// sum_{n<M} exp(j 2 pi n (f - idx/N)) * exp(j 2 pi idx c / N), the map value at bin
+// idx of a unit tone f along one axis (c: the centring offset, (M - 1)/2 or 0),
+// with the Dirichlet sum in closed form: exp(j pi (M - 1) r) sin(pi M r) / sin(pi r),
+// r = f - idx/N reduced to [-1/2, 1/2] (the sum has period one in r).  FP64.
+__device__ dcplx tone_bin(double f, int m, int n, int idx, double c) {
+    const double x = f - (double)idx / n;
+    const double r = x - rint(x);
+    const double ratio = fabs(r) < 1e-15 ? (double)m : sinpi(m * r) / sinpi(r);
+    double sn, cs;
+    sincospi((m - 1) * r + 2.0 * idx * c / n, &sn, &cs);
+    return {cs * ratio, sn * ratio};
+}
+
+constexpr int kResRows = 8;          // map rows per workgroup of the residual maps
+constexpr int kResTable = 4096;      // Doppler-axis values (atoms x N_d) held in LDS
+
+// Z_res[q][i][l] = Z_y[q][i][l] - sum_t alpha[t][q] R_t[i] D_t[l], where the maps of
+// the atom A(theta_t) = b(f_d) (x) a(f_r) are R_t[i] D_t[l] with R, D the
+// single-axis tone values above.  Grid (N_r / kResRows, K).
+__global__ __launch_bounds__(kThreads) void bomp_resid_maps_kernel(Geom g, GridP gp,
+                                                                  const float2* __restrict__ maps_y,
+                                                                  const int64_t* __restrict__ support, int nsel,
+                                                                  const float2* __restrict__ alpha,
+                                                                  float2* __restrict__ out) {
+    __shared__ double fr[kMaxSupport], fd[kMaxSupport];
+    __shared__ float2 dv[kResTable];
+    __shared__ float2 cr[kMaxSupport][kResRows];
+    const int q = blockIdx.y, i0 = blockIdx.x * kResRows, tid = threadIdx.x;
+    const int nd = g.nd;
+    if (tid < nsel) cell_freqs(g, gp, q, support[tid], fr[tid], fd[tid]);
+    __syncthreads();
+    const double cs = g.centered ? 0.5 * (g.ms - 1) : 0.0, cm = g.centered ? 0.5 * (g.mc - 1) : 0.0;
+    for (int e = tid; e < nsel * nd; e += kThreads) {
+        const int t = e >> g.log2_nd, l = e & (nd - 1);
+        const dcplx d = tone_bin(fd[t], g.mc, nd, l, cm);
+        dv[e] = make_float2((float)d.x, (float)d.y);
+    }
+    for (int e = tid; e < nsel * kResRows; e += kThreads) {
+        const int t = e / kResRows, ii = e - t * kResRows;
+        const dcplx rv = tone_bin(fr[t], g.ms, g.nr, i0 + ii, cs);
+        const float2 a = alpha[(size_t)t * g.k + q];
+        const dcplx ar = dmul({(double)a.x, (double)a.y}, rv);
+        cr[t][ii] = make_float2((float)ar.x, (float)ar.y);
+    }
+    __syncthreads();
+    const size_t base = ((size_t)q * g.nr + i0) * nd;
+    for (int e = tid; e < kResRows * nd; e += kThreads) {
+        const int ii = e >> g.log2_nd, l = e & (nd - 1);
+        float2 v = maps_y[base + e];
+        for (int t = 0; t < nsel; ++t) {
+            const float2 c = cr[t][ii], d = dv[t * nd + l];
+            v.x -= c.x * d.x - c.y * d.y;
+            v.y -= c.x * d.y + c.y * d.x;
+        }
+        out[base + e] = v;
+    }
+}
+
 }  // namespace
+
+bool bomp_resid_maps_ok(const Geom& g, int nsel) {
+    return nsel >= 1 && nsel <= kMaxSupport && (long)nsel * g.nd <= kResTable && g.nr % kResRows == 0;
+}
+
+hipError_t launch_bomp_resid_maps(const Geom& g, const GridP& gp, const float2* maps_y, const int64_t* support,
+                                  int nsel, const float2* alpha, float2* out, hipStream_t st) {
+    hipLaunchKernelGGL(bomp_resid_maps_kernel, dim3(g.nr / kResRows, g.k), dim3(kThreads), 0, st, g, gp, maps_y,
+                       support, nsel, alpha, out);
+    return hipGetLastError();
+}
 
 size_t bomp_fit_ws_bytes(const Geom& g) {
     return (size_t)g.k * (g.mc / kRowsPerChunk) * kMaxSupport * sizeof(double2);

@@ -318,6 +318,13 @@ hipError_t launch_direct(const Geom& g, const GridP& gp, const float2* y, int ge
                          gh_peak* block, const int64_t* excl, int nexcl, hipStream_t st);
 
 size_t bomp_fit_ws_bytes(const Geom& g);
+// Maps of the residual Y - sum_t alpha_t A(theta_t) from the maps of Y by
+// linearity: the maps of an atom are a closed-form outer product (the
+// Dirichlet sums of eqs. (1)-(3) along range and Doppler).  Applies while
+// nsel * N_d fits the kernel's table (bomp_resid_maps_ok).
+bool bomp_resid_maps_ok(const Geom& g, int nsel);
+hipError_t launch_bomp_resid_maps(const Geom& g, const GridP& gp, const float2* maps_y, const int64_t* support,
+                                  int nsel, const float2* alpha, float2* out, hipStream_t st);
 hipError_t launch_bomp_fit(const Geom& g, const GridP& gp, const float2* y, float2* resid,
                            const int64_t* support, int nsel, float2* alpha, void* ws, hipStream_t st);
 

@@ -361,6 +361,45 @@ def test_bomp_select_then_fit_equals_step(use_direct):
         assert torch.equal(u, v), f"after reset: {name}"
 
 
+def _resid_maps_view(st, radar, grid_s):
+    """The residual maps gh_bomp_select builds in the workspace (after the block
+    peaks and the fit's partial sums, each rounded up to 256 bytes)."""
+    a256 = lambda v: (v + 255) // 256 * 256
+    off = a256(grid_s.n[0] * grid_s.n[1] * 16) + a256(radar.k * (radar.mc // 8) * gh.MAX_SUPPORT * 16)
+    nbytes = radar.k * radar.nr * radar.nd * 8
+    return st.ws[off:off + nbytes].view(torch.complex64).view(radar.k, radar.nr, radar.nd)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_bomp_residual_maps_closed_form(cfg, monkeypatch):
+    """Maps of the residual from the maps of y and the fitted atoms in closed form,
+    against the FFT of the residual (per receiver, relative Frobenius <= 1e-5), and
+    the same selections as with the FFT of the residual (GH_BOMP_MAPS=fft)."""
+    say(f"bomp residual maps cfg={cfg}")
+    s, r, gr = scene_and_radar(cfg, 0)
+    grid = gh.grid_of(s.grid)
+    y = to_dev(s.y)
+    st = gh.BompState(gr, grid, y, max_support=3)
+    st.step()
+    st.step()
+    st.select()
+    torch.cuda.synchronize()
+    z_closed = _resid_maps_view(st, gr, s.grid).cpu().numpy().astype(np.complex128)
+    z_fft = gh.rd_maps(gr, st.resid).cpu().numpy().astype(np.complex128)
+    for q in range(gr.k):
+        err = np.linalg.norm(z_closed[q] - z_fft[q]) / np.linalg.norm(z_fft[q])
+        say(f"  receiver {q}: {err:.3g}")
+        assert err <= 1e-5, (q, err)
+    st.fit()
+    monkeypatch.setenv("GH_BOMP_MAPS", "fft")
+    ref = gh.BompState(gr, grid, y, max_support=3)
+    for _ in range(3):
+        ref.step()
+    torch.cuda.synchronize()
+    assert torch.equal(st.support, ref.support)
+    assert torch.equal(st.alpha, ref.alpha)
+
+
 # ---------------------------------------------------------------- refinement
 
 @pytest.mark.parametrize("kernel", ["cluster", "single"])
