@@ -180,9 +180,10 @@ size_t gh_bomp_workspace_bytes(const gh_radar *radar, const gh_grid *grid, int32
  *      maps of the residual: at n_support == 0 gh_rd_maps of d_y, written to
  *      d_maps; later, by linearity of the maps, those of y in d_maps minus
  *      sum_t alpha_t R_t[i] D_t[l], the maps of the fitted atoms in closed
- *      form (Dirichlet sums along range and Doppler, FP64, applied in FP32),
- *      built in the workspace (or gh_rd_maps of d_resid there when
- *      n_support * N_d exceeds 4096);
+ *      form (Dirichlet sums along range and Doppler in FP64, left in the
+ *      workspace by the previous fit; applied in FP32), built in the
+ *      workspace (or gh_rd_maps of d_resid there when n_support * N_d
+ *      exceeds 4096);
  *   2. select the maximum over the grid excluding the n_support cells already
  *      in d_support; store its index at d_support[n_support];
  *   3. for each receiver, least squares over the n_support + 1 selected cells
@@ -194,8 +195,9 @@ size_t gh_bomp_workspace_bytes(const gh_radar *radar, const gh_grid *grid, int32
  * d_maps: complex64 map buffer [K][N_r][N_d] (grid hopping: written at
  * n_support == 0 and read by the later iterations of the run, so the caller
  * passes the same buffer, unchanged, throughout; may be NULL when
- * use_direct == 1).  d_alpha: read at n_support >= 1 (the previous
- * iteration's fit), written by the fit.  d_support: int64 [max_support], in/out.
+ * use_direct == 1).  d_ws carries the fitted atoms' maps from one
+ * iteration to the next: pass the same workspace throughout a run.
+ * d_support: int64 [max_support], in/out.
  * 0 <= n_support < max_support <= GH_MAX_SUPPORT.  d_selected: gh_peak [1]
  * (NULL: not written), the selected maximum.  Everything stays on the
  * device; no host synchronisation inside.  The same as gh_bomp_select
@@ -205,19 +207,19 @@ int gh_bomp_step(const gh_radar *radar, const gh_grid *grid, const void *d_y, vo
                  int32_t n_support, int32_t max_support, void *d_alpha, gh_peak *d_selected,
                  void *d_ws, size_t ws_bytes, void *stream);
 
-/* Steps 1 and 2 of gh_bomp_step alone (arguments as there; d_alpha is only
- * read): after it, d_support[0 .. n_support] holds the selection.  Lets a
- * caller start work that needs only the selected cells (gh_refine) before
- * the fit. */
+/* Steps 1 and 2 of gh_bomp_step alone (arguments as there): after it,
+ * d_support[0 .. n_support] holds the selection.  Lets a caller start work
+ * that needs only the selected cells (gh_refine) before the fit. */
 int gh_bomp_select(const gh_radar *radar, const gh_grid *grid, const void *d_y, const void *d_resid,
                    void *d_maps, int32_t use_direct, int32_t interp, int32_t gemm_dtype, int64_t *d_support,
-                   int32_t n_support, int32_t max_support, const void *d_alpha, gh_peak *d_selected, void *d_ws,
-                   size_t ws_bytes, void *stream);
+                   int32_t n_support, int32_t max_support, gh_peak *d_selected, void *d_ws, size_t ws_bytes,
+                   void *stream);
 
 /* Steps 3 and 4 of gh_bomp_step alone: least squares over the n_selected
  * cells d_support[0 .. n_selected) (1 <= n_selected <= max_support <=
  * GH_MAX_SUPPORT), alpha (complex64 [n_selected][K]) to d_alpha, and
- * d_resid <- Y - sum_t alpha_t A(theta_t).  d_ws: a workspace of
+ * d_resid <- Y - sum_t alpha_t A(theta_t); the fitted atoms' maps are left
+ * in the workspace for the next selection.  d_ws: the run's workspace, of
  * gh_bomp_workspace_bytes(radar, grid, use_direct, gemm_dtype) bytes for any
  * use_direct and gemm_dtype (this call uses the part they share); it must not
  * be in use by a gh_bomp_select or gh_bomp_step still running on another

@@ -285,7 +285,8 @@ size_t gh_bomp_workspace_bytes(const gh_radar* radar, const gh_grid* grid, int32
     gh::GridP gp;
     if (make_geom(radar, g) || make_grid(grid, gp) || check_gemm(gemm_dtype)) return 0;
     ok();
-    size_t b = align256((size_t)gp.nloc * sizeof(gh_peak)) + align256(gh::bomp_fit_ws_bytes(g));
+    size_t b = align256((size_t)gp.nloc * sizeof(gh_peak)) + align256(gh::bomp_fit_ws_bytes(g)) +
+               align256(gh::bomp_atom_vec_bytes(g));
     if (use_direct)
         b += align256(gh::direct_ws_bytes(g, gp, gemm_dtype));
     else
@@ -308,17 +309,20 @@ static int bomp_common(const gh_radar* radar, const gh_grid* grid, int32_t use_d
 // Decision on the residual (y itself at n_support == 0) and selection into
 // support[n_support].  Grid hopping: the maps of y go to d_maps at
 // n_support == 0; later, the maps of the residual are built in the workspace
-// from them and the fitted atoms (closed form), or by the FFT of the residual
-// where the closed-form table does not fit (or GH_BOMP_MAPS=fft, diagnostics).
+// from them and the atom maps the previous fit left in the workspace, or by
+// the FFT of the residual where the atoms' Doppler table does not fit (or
+// with GH_BOMP_MAPS=fft, diagnostics).
 // Arguments already checked.
 static hipError_t bomp_select_launch(const gh::Geom& g, const gh::GridP& gp, const void* d_y, const void* d_resid,
                                      void* d_maps, int32_t use_direct, int32_t interp, int32_t gemm_dtype,
-                                     int64_t* d_support, int32_t n_support, const void* d_alpha,
-                                     gh_peak* d_selected, char* ws, hipStream_t st) {
+                                     int64_t* d_support, int32_t n_support, gh_peak* d_selected, char* ws,
+                                     hipStream_t st) {
     const float2* src = (const float2*)(n_support == 0 ? d_y : d_resid);
     gh_peak* block = (gh_peak*)ws;
     ws += align256((size_t)gp.nloc * sizeof(gh_peak));
     ws += align256(gh::bomp_fit_ws_bytes(g));
+    const float2* atom_vec = (const float2*)ws;
+    ws += align256(gh::bomp_atom_vec_bytes(g));
     hipError_t e;
     if (use_direct) {
         e = gh::launch_direct(g, gp, src, gemm_dtype, ws, nullptr, block, d_support, n_support, st);
@@ -331,8 +335,7 @@ static hipError_t bomp_select_launch(const gh::Geom& g, const gh::GridP& gp, con
         const bool fft_only = mode && strcmp(mode, "fft") == 0;
         float2* rmaps = (float2*)ws;
         if (!fft_only && gh::bomp_resid_maps_ok(g, n_support))
-            e = gh::launch_bomp_resid_maps(g, gp, (const float2*)d_maps, d_support, n_support, (const float2*)d_alpha,
-                                           rmaps, st);
+            e = gh::launch_bomp_resid_maps(g, (const float2*)d_maps, atom_vec, n_support, rmaps, st);
         else
             e = gh::launch_rd_maps(g, src, rmaps, GH_MAP_C64, st);
         if (e == hipSuccess)
@@ -345,9 +348,10 @@ static hipError_t bomp_select_launch(const gh::Geom& g, const gh::GridP& gp, con
 static hipError_t bomp_fit_launch(const gh::Geom& g, const gh::GridP& gp, const void* d_y, void* d_resid,
                                   const int64_t* d_support, int32_t n_selected, void* d_alpha, char* ws,
                                   hipStream_t st) {
-    void* fit_ws = ws + align256((size_t)gp.nloc * sizeof(gh_peak));
+    char* fit_ws = ws + align256((size_t)gp.nloc * sizeof(gh_peak));
+    float2* atom_vec = (float2*)(fit_ws + align256(gh::bomp_fit_ws_bytes(g)));
     return gh::launch_bomp_fit(g, gp, (const float2*)d_y, (float2*)d_resid, d_support, n_selected,
-                               (float2*)d_alpha, fit_ws, st);
+                               (float2*)d_alpha, fit_ws, atom_vec, st);
 }
 
 static int bomp_select_checks(const gh::GridP& gp, const void* d_y, const void* d_resid, const void* d_maps,
@@ -379,7 +383,7 @@ int gh_bomp_step(const gh_radar* radar, const gh_grid* grid, const void* d_y, vo
     if ((rc = check_device())) return rc;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = bomp_select_launch(g, gp, d_y, d_resid, d_maps, use_direct, interp, gemm_dtype, d_support,
-                                      n_support, d_alpha, d_selected, (char*)d_ws, st);
+                                      n_support, d_selected, (char*)d_ws, st);
     if (e == hipSuccess) e = bomp_fit_launch(g, gp, d_y, d_resid, d_support, n_support + 1, d_alpha, (char*)d_ws, st);
     if (e != hipSuccess) return hip_fail(e, "gh_bomp_step launch");
     return ok();
@@ -387,8 +391,7 @@ int gh_bomp_step(const gh_radar* radar, const gh_grid* grid, const void* d_y, vo
 
 int gh_bomp_select(const gh_radar* radar, const gh_grid* grid, const void* d_y, const void* d_resid, void* d_maps,
                    int32_t use_direct, int32_t interp, int32_t gemm_dtype, int64_t* d_support, int32_t n_support,
-                   int32_t max_support, const void* d_alpha, gh_peak* d_selected, void* d_ws, size_t ws_bytes,
-                   void* stream) {
+                   int32_t max_support, gh_peak* d_selected, void* d_ws, size_t ws_bytes, void* stream) {
     gh::Geom g;
     gh::GridP gp;
     int rc = bomp_common(radar, grid, use_direct, interp, gemm_dtype, max_support, g, gp);
@@ -396,13 +399,11 @@ int gh_bomp_select(const gh_radar* radar, const gh_grid* grid, const void* d_y, 
     if ((rc = bomp_select_checks(gp, d_y, d_resid, d_maps, use_direct, d_support, n_support, max_support, d_selected,
                                  d_ws)))
         return rc;
-    if (n_support > 0 && !d_alpha) return fail(GH_EINVAL, "NULL device pointer");
-    if ((rc = check_aligned({d_alpha}))) return rc;
     const size_t need = gh_bomp_workspace_bytes(radar, grid, use_direct, gemm_dtype);
     if (ws_bytes < need) return fail(GH_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if ((rc = check_device())) return rc;
     const hipError_t e = bomp_select_launch(g, gp, d_y, d_resid, d_maps, use_direct, interp, gemm_dtype, d_support,
-                                            n_support, d_alpha, d_selected, (char*)d_ws, (hipStream_t)stream);
+                                            n_support, d_selected, (char*)d_ws, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gh_bomp_select launch");
     return ok();
 }
@@ -418,7 +419,9 @@ int gh_bomp_fit(const gh_radar* radar, const gh_grid* grid, const void* d_y, voi
     if (n_selected < 1 || n_selected > max_support)
         return fail(GH_EINVAL, "n_selected = %d must be in [1, max_support]", n_selected);
     if (n_selected > gp.nloc * (long long)gp.nv) return fail(GH_EINVAL, "support larger than the grid");
-    const size_t need = gh_bomp_workspace_bytes(radar, grid, 0, GH_GEMM_F32);
+    // the part every Block-OMP workspace layout shares: block peaks, fit partials, atom maps
+    const size_t need = align256((size_t)gp.nloc * sizeof(gh_peak)) + align256(gh::bomp_fit_ws_bytes(g)) +
+                        align256(gh::bomp_atom_vec_bytes(g));
     if (ws_bytes < need) return fail(GH_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if ((rc = check_device())) return rc;
     const hipError_t e = bomp_fit_launch(g, gp, d_y, d_resid, d_support, n_selected, d_alpha, (char*)d_ws,

@@ -192,6 +192,19 @@ __device__ void solve_fit(const Geom& g, const GridP& gp, int q, const int64_t* 
     __syncthreads();
 }
 
+// sum_{n<M} exp(j 2 pi n (f - idx/N)) * exp(j 2 pi idx c / N), the map value at bin
+// idx of a unit tone f along one axis (c: the centring offset, (M - 1)/2 or 0),
+// with the Dirichlet sum in closed form: exp(j pi (M - 1) r) sin(pi M r) / sin(pi r),
+// r = f - idx/N reduced to [-1/2, 1/2] (the sum has period one in r).  FP64.
+__device__ dcplx tone_bin(double f, int m, int n, int idx, double c) {
+    const double x = f - (double)idx / n;
+    const double r = x - rint(x);
+    const double ratio = fabs(r) < 1e-15 ? (double)m : sinpi(m * r) / sinpi(r);
+    double sn, cs;
+    sincospi((m - 1) * r + 2.0 * idx * c / n, &sn, &cs);
+    return {cs * ratio, sn * ratio};
+}
+
 // Fit and residual of receiver blockIdx.y: every workgroup solves the (small)
 // least squares itself, workgroup 0 also writes alpha (complex64 [nsel][K]), then
 //   resid[q][m][s] = y[q][m][s] - sum_t alpha[t][q] exp(+j 2 pi (f_r,t s + f_d,t m)).
@@ -199,7 +212,8 @@ __global__ __launch_bounds__(kThreads) void bomp_fit_residual_kernel(Geom g, Gri
                                                                     float2* __restrict__ resid,
                                                                     const int64_t* __restrict__ support, int nsel,
                                                                     const double2* __restrict__ part,
-                                                                    float2* __restrict__ alpha) {
+                                                                    float2* __restrict__ alpha,
+                                                                    float2* __restrict__ atom_vec) {
     __shared__ FitShared sh;
     __shared__ float2 al[kMaxSupport];
     const int q = blockIdx.y;
@@ -223,51 +237,45 @@ __global__ __launch_bounds__(kThreads) void bomp_fit_residual_kernel(Geom g, Gri
         }
         resid[(size_t)q * n + e] = v;
     }
-}
-
-// sum_{n<M} exp(j 2 pi n (f - idx/N)) * exp(j 2 pi idx c / N), the map value at bin
-// idx of a unit tone f along one axis (c: the centring offset, (M - 1)/2 or 0),
-// with the Dirichlet sum in closed form: exp(j pi (M - 1) r) sin(pi M r) / sin(pi r),
-// r = f - idx/N reduced to [-1/2, 1/2] (the sum has period one in r).  FP64.
-__device__ dcplx tone_bin(double f, int m, int n, int idx, double c) {
-    const double x = f - (double)idx / n;
-    const double r = x - rint(x);
-    const double ratio = fabs(r) < 1e-15 ? (double)m : sinpi(m * r) / sinpi(r);
-    double sn, cs;
-    sincospi((m - 1) * r + 2.0 * idx * c / n, &sn, &cs);
-    return {cs * ratio, sn * ratio};
+    // the maps of each fitted atom of receiver q, alpha_t R_t[i] and D_t[l]
+    // (atom_vec[q][t][0 .. N_r) and [N_r .. N_r + N_d)), for the next selection
+    const int len = g.nr + g.nd;
+    const double cs = g.centered ? 0.5 * (g.ms - 1) : 0.0, cm = g.centered ? 0.5 * (g.mc - 1) : 0.0;
+    for (int e = blockIdx.x * kThreads + threadIdx.x; e < nsel * len; e += gridDim.x * kThreads) {
+        const int t = e / len, j = e - t * len;
+        float2 v;
+        if (j < g.nr) {
+            const dcplx r = dmul({(double)al[t].x, (double)al[t].y}, tone_bin(sh.fr[t], g.ms, g.nr, j, cs));
+            v = make_float2((float)r.x, (float)r.y);
+        } else {
+            const dcplx d = tone_bin(sh.fd[t], g.mc, g.nd, j - g.nr, cm);
+            v = make_float2((float)d.x, (float)d.y);
+        }
+        atom_vec[((size_t)q * kMaxSupport + t) * len + j] = v;
+    }
 }
 
 constexpr int kResRows = 8;          // map rows per workgroup of the residual maps
 constexpr int kResTable = 4096;      // Doppler-axis values (atoms x N_d) held in LDS
 
-// Z_res[q][i][l] = Z_y[q][i][l] - sum_t alpha[t][q] R_t[i] D_t[l], where the maps of
-// the atom A(theta_t) = b(f_d) (x) a(f_r) are R_t[i] D_t[l] with R, D the
-// single-axis tone values above.  Grid (N_r / kResRows, K).
-__global__ __launch_bounds__(kThreads) void bomp_resid_maps_kernel(Geom g, GridP gp,
-                                                                  const float2* __restrict__ maps_y,
-                                                                  const int64_t* __restrict__ support, int nsel,
-                                                                  const float2* __restrict__ alpha,
+// Z_res[q][i][l] = Z_y[q][i][l] - sum_t (alpha_t R_t)[i] D_t[l], where the maps of
+// the atom A(theta_t) = b(f_d) (x) a(f_r) are R_t[i] D_t[l] (the single-axis tone
+// values above, written by the fit with alpha applied).  Grid (N_r / kResRows, K).
+__global__ __launch_bounds__(kThreads) void bomp_resid_maps_kernel(Geom g, const float2* __restrict__ maps_y,
+                                                                  const float2* __restrict__ atom_vec, int nsel,
                                                                   float2* __restrict__ out) {
-    __shared__ double fr[kMaxSupport], fd[kMaxSupport];
     __shared__ float2 dv[kResTable];
     __shared__ float2 cr[kMaxSupport][kResRows];
     const int q = blockIdx.y, i0 = blockIdx.x * kResRows, tid = threadIdx.x;
-    const int nd = g.nd;
-    if (tid < nsel) cell_freqs(g, gp, q, support[tid], fr[tid], fd[tid]);
-    __syncthreads();
-    const double cs = g.centered ? 0.5 * (g.ms - 1) : 0.0, cm = g.centered ? 0.5 * (g.mc - 1) : 0.0;
+    const int nd = g.nd, len = g.nr + g.nd;
+    const float2* av = atom_vec + (size_t)q * kMaxSupport * len;
     for (int e = tid; e < nsel * nd; e += kThreads) {
         const int t = e >> g.log2_nd, l = e & (nd - 1);
-        const dcplx d = tone_bin(fd[t], g.mc, nd, l, cm);
-        dv[e] = make_float2((float)d.x, (float)d.y);
+        dv[e] = av[(size_t)t * len + g.nr + l];
     }
     for (int e = tid; e < nsel * kResRows; e += kThreads) {
         const int t = e / kResRows, ii = e - t * kResRows;
-        const dcplx rv = tone_bin(fr[t], g.ms, g.nr, i0 + ii, cs);
-        const float2 a = alpha[(size_t)t * g.k + q];
-        const dcplx ar = dmul({(double)a.x, (double)a.y}, rv);
-        cr[t][ii] = make_float2((float)ar.x, (float)ar.y);
+        cr[t][ii] = av[(size_t)t * len + i0 + ii];
     }
     __syncthreads();
     const size_t base = ((size_t)q * g.nr + i0) * nd;
@@ -289,10 +297,12 @@ bool bomp_resid_maps_ok(const Geom& g, int nsel) {
     return nsel >= 1 && nsel <= kMaxSupport && (long)nsel * g.nd <= kResTable && g.nr % kResRows == 0;
 }
 
-hipError_t launch_bomp_resid_maps(const Geom& g, const GridP& gp, const float2* maps_y, const int64_t* support,
-                                  int nsel, const float2* alpha, float2* out, hipStream_t st) {
-    hipLaunchKernelGGL(bomp_resid_maps_kernel, dim3(g.nr / kResRows, g.k), dim3(kThreads), 0, st, g, gp, maps_y,
-                       support, nsel, alpha, out);
+size_t bomp_atom_vec_bytes(const Geom& g) { return (size_t)g.k * kMaxSupport * (g.nr + g.nd) * sizeof(float2); }
+
+hipError_t launch_bomp_resid_maps(const Geom& g, const float2* maps_y, const float2* atom_vec, int nsel, float2* out,
+                                  hipStream_t st) {
+    hipLaunchKernelGGL(bomp_resid_maps_kernel, dim3(g.nr / kResRows, g.k), dim3(kThreads), 0, st, g, maps_y, atom_vec,
+                       nsel, out);
     return hipGetLastError();
 }
 
@@ -301,7 +311,7 @@ size_t bomp_fit_ws_bytes(const Geom& g) {
 }
 
 hipError_t launch_bomp_fit(const Geom& g, const GridP& gp, const float2* y, float2* resid, const int64_t* support,
-                           int nsel, float2* alpha, void* ws, hipStream_t st) {
+                           int nsel, float2* alpha, void* ws, float2* atom_vec, hipStream_t st) {
     double2* part = static_cast<double2*>(ws);
     hipLaunchKernelGGL(bomp_rhs_kernel, dim3(g.mc / kRowsPerChunk, g.k), dim3(kThreads), 0, st, g, gp, y, support,
                        nsel, part);
@@ -314,7 +324,7 @@ hipError_t launch_bomp_fit(const Geom& g, const GridP& gp, const float2* y, floa
     const int cap = kResidWorkgroups / g.k > 0 ? kResidWorkgroups / g.k : 1;
     if (per_q > cap) per_q = cap;
     hipLaunchKernelGGL(bomp_fit_residual_kernel, dim3(per_q, g.k), dim3(kThreads), 0, st, g, gp, y, resid, support,
-                       nsel, part, alpha);
+                       nsel, part, alpha, atom_vec);
     return hipGetLastError();
 }
 

@@ -318,15 +318,19 @@ hipError_t launch_direct(const Geom& g, const GridP& gp, const float2* y, int ge
                          gh_peak* block, const int64_t* excl, int nexcl, hipStream_t st);
 
 size_t bomp_fit_ws_bytes(const Geom& g);
-// Maps of the residual Y - sum_t alpha_t A(theta_t) from the maps of Y by
-// linearity: the maps of an atom are a closed-form outer product (the
-// Dirichlet sums of eqs. (1)-(3) along range and Doppler).  Applies while
-// nsel * N_d fits the kernel's table (bomp_resid_maps_ok).
-bool bomp_resid_maps_ok(const Geom& g, int nsel);
-hipError_t launch_bomp_resid_maps(const Geom& g, const GridP& gp, const float2* maps_y, const int64_t* support,
-                                  int nsel, const float2* alpha, float2* out, hipStream_t st);
+// The fit also writes, per receiver and fitted atom, the atom's maps as an
+// outer product alpha_t R_t[i] D_t[l] (closed-form Dirichlet sums along range
+// and Doppler): atom_vec [K][GH_MAX_SUPPORT][N_r + N_d] complex64.
+size_t bomp_atom_vec_bytes(const Geom& g);
 hipError_t launch_bomp_fit(const Geom& g, const GridP& gp, const float2* y, float2* resid,
-                           const int64_t* support, int nsel, float2* alpha, void* ws, hipStream_t st);
+                           const int64_t* support, int nsel, float2* alpha, void* ws, float2* atom_vec,
+                           hipStream_t st);
+// Maps of the residual Y - sum_t alpha_t A(theta_t) from the maps of Y by
+// linearity, with the atom vectors of the last fit.  Applies while nsel * N_d
+// fits the kernel's table (bomp_resid_maps_ok).
+bool bomp_resid_maps_ok(const Geom& g, int nsel);
+hipError_t launch_bomp_resid_maps(const Geom& g, const float2* maps_y, const float2* atom_vec, int nsel, float2* out,
+                                  hipStream_t st);
 
 size_t refine_ws_bytes(const Geom& g, int ncells);
 hipError_t launch_refine(const Geom& g, const GridP& gp, const float2* y, const int64_t* cells, int ncells,

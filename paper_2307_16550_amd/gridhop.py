@@ -90,7 +90,7 @@ def load():
     lib.gh_bomp_workspace_bytes.argtypes = [rp, gp_, i32, i32]
     lib.gh_bomp_workspace_bytes.restype = sz
     lib.gh_bomp_step.argtypes = [rp, gp_, vp, vp, vp, i32, i32, i32, vp, i32, i32, vp, pp, vp, sz, vp]
-    lib.gh_bomp_select.argtypes = [rp, gp_, vp, vp, vp, i32, i32, i32, vp, i32, i32, vp, pp, vp, sz, vp]
+    lib.gh_bomp_select.argtypes = [rp, gp_, vp, vp, vp, i32, i32, i32, vp, i32, i32, pp, vp, sz, vp]
     lib.gh_bomp_fit.argtypes = [rp, gp_, vp, vp, vp, i32, i32, vp, vp, sz, vp]
     lib.gh_refine_workspace_bytes.argtypes = [rp, gp_, i32]
     lib.gh_refine_workspace_bytes.restype = sz
@@ -325,8 +325,8 @@ class BompState:
         lib = load()
         _check(lib.gh_bomp_select(ctypes.byref(self.radar.c_struct), ctypes.byref(self.grid), _ptr(self.y),
                                   _ptr(self.resid), _ptr(self.maps), self.use_direct, self.interp, self.gemm,
-                                  _ptr(self.support), self.n, self.max_support, _ptr(self.alpha),
-                                  _ptr(self.selected), _ptr(self.ws), self.ws.numel(), _stream(stream)))
+                                  _ptr(self.support), self.n, self.max_support, _ptr(self.selected),
+                                  _ptr(self.ws), self.ws.numel(), _stream(stream)))
         self._selected_pending = True
 
     def fit(self, stream=None):

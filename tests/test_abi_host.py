@@ -123,16 +123,14 @@ def test_bomp_select_and_fit_argument_checks(lib):
     r = radar()
     ws = lib.gh_bomp_workspace_bytes(ctypes.byref(r.c_struct), ctypes.byref(GRID), 0, 0)
     sargs = [ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, None, FAKE, 0, 0, 0, FAKE]
-    assert lib.gh_bomp_select(*sargs, 1, 3, FAKE, None, FAKE, ws, None) == gh.GH_EINVAL  # residual needed past 0
-    assert lib.gh_bomp_select(*sargs, 3, 3, FAKE, None, FAKE, ws, None) == gh.GH_EINVAL  # n_support == max
-    assert lib.gh_bomp_select(*sargs, 0, 3, None, None, FAKE, ws - 1, None) == gh.GH_EWORKSPACE  # y alone at 0
-    rargs = [ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, FAKE, FAKE, 0, 0, 0, FAKE]
-    assert lib.gh_bomp_select(*rargs, 1, 3, None, None, FAKE, ws, None) == gh.GH_EINVAL  # alpha needed past 0
+    assert lib.gh_bomp_select(*sargs, 1, 3, None, FAKE, ws, None) == gh.GH_EINVAL        # residual needed past 0
+    assert lib.gh_bomp_select(*sargs, 3, 3, None, FAKE, ws, None) == gh.GH_EINVAL        # n_support == max
+    assert lib.gh_bomp_select(*sargs, 0, 3, None, FAKE, ws - 1, None) == gh.GH_EWORKSPACE  # y alone at 0
     fargs = [ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, FAKE, FAKE]
     assert lib.gh_bomp_fit(*fargs, 0, 3, FAKE, FAKE, ws, None) == gh.GH_EINVAL           # nothing selected
     assert lib.gh_bomp_fit(*fargs, 4, 3, FAKE, FAKE, ws, None) == gh.GH_EINVAL           # above max_support
     assert lib.gh_bomp_fit(*fargs, 1, 3, None, FAKE, ws, None) == gh.GH_EINVAL           # alpha NULL
-    assert lib.gh_bomp_fit(*fargs, 1, 3, FAKE, FAKE, ws - 1, None) == gh.GH_EWORKSPACE
+    assert lib.gh_bomp_fit(*fargs, 1, 3, FAKE, FAKE, 256, None) == gh.GH_EWORKSPACE
 
 
 def test_error_message_cleared_after_success(lib):

@@ -363,9 +363,10 @@ def test_bomp_select_then_fit_equals_step(use_direct):
 
 def _resid_maps_view(st, radar, grid_s):
     """The residual maps gh_bomp_select builds in the workspace (after the block
-    peaks and the fit's partial sums, each rounded up to 256 bytes)."""
+    peaks, the fit's partial sums and the atom maps, each rounded up to 256 bytes)."""
     a256 = lambda v: (v + 255) // 256 * 256
-    off = a256(grid_s.n[0] * grid_s.n[1] * 16) + a256(radar.k * (radar.mc // 8) * gh.MAX_SUPPORT * 16)
+    off = (a256(grid_s.n[0] * grid_s.n[1] * 16) + a256(radar.k * (radar.mc // 8) * gh.MAX_SUPPORT * 16)
+           + a256(radar.k * gh.MAX_SUPPORT * (radar.nr + radar.nd) * 8))
     nbytes = radar.k * radar.nr * radar.nd * 8
     return st.ws[off:off + nbytes].view(torch.complex64).view(radar.k, radar.nr, radar.nd)
 
