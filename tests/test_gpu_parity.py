@@ -321,6 +321,30 @@ def test_bomp_three_iterations_cfg1(use_direct, gemm):
         resid_ref = resid_ref.astype(np.complex64)
 
 
+def test_bomp_long_doppler_axis():
+    """N_d = 2048: the residual maps come from the closed form while the atoms'
+    Doppler tables fit (two atoms, 4096 values) and from the FFT of the
+    residual after that (three atoms); every selection against the oracle."""
+    say("bomp N_d = 2048")
+    s, r, gr = scene_and_radar(1, 8, mc=512, ms=32, targets=4, snr_db=20.0)
+    assert gr.nd == 2048
+    st = gh.BompState(gr, gh.grid_of(s.grid), to_dev(s.y), max_support=4, interp=gh.BILINEAR)
+    sup_ref, resid_ref = [], s.y
+    for it in range(4):
+        st.step()
+        torch.cuda.synchronize()
+        sup_gpu = st.support.cpu().numpy()[: it + 1].tolist()
+        d = obomp.decision(resid_ref, r, s.grid, False, ogh.BILINEAR)
+        val, cell = opeaks.global_peak(d, exclude=sup_ref)
+        flat = d.ravel()
+        check_argmax(lambda i: flat[i], sup_gpu[it], cell, val, f"bomp N_d=2048 it {it}", TIE_TOL)
+        sup_ref = sup_gpu
+        alpha_ref, resid_ref = obomp.fit(s.y, r, s.grid, sup_ref)
+        ag = st.alpha.cpu().numpy()[: it + 1]
+        assert np.max(np.abs(ag - alpha_ref)) <= 1e-4 * np.max(np.abs(alpha_ref))
+        resid_ref = resid_ref.astype(np.complex64)
+
+
 def test_bomp_fit_cfg2_full_size():
     say("bomp cfg2")
     s, r, gr = scene_and_radar(2)
