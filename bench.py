@@ -17,11 +17,11 @@ Grid points evaluated per step: 4 x 16,777,216 (grid hopping) + 1,048,576
 (direct).  `value` is that count divided by the measured step time.  The
 step is captured once in a HIP graph (kernel launches and one device copy;
 no memset) and the timed steps are graph replays.  Rows 1-2, row 3 and rows
-4-5 are three independent chains: by default (`--streams 2`) row 3 runs on a
-second stream beside the Block-OMP iterations, and rows 1-2 (after the last
-Block-OMP fit, which the refinement does not need) on that stream beside the
-refinement; the second stream is forked from and joined back into the
-capture stream.  `--streams 1` captures everything on one stream in the
+4-5 are three independent chains: by default (`--streams 2`) row 3 and the
+maps of row 1 run on a second stream beside the Block-OMP iterations, and the
+rest of rows 1-2 (after the last Block-OMP fit, which the refinement does not
+need) on that stream beside the refinement; the second stream is forked from
+and joined back into the capture stream.  `--streams 1` captures everything on one stream in the
 order above.  The
 per-row times come from eager one-stream steps with HIP events, and after
 the replays the step's outputs (argmax cells, Block-OMP support and
@@ -384,9 +384,10 @@ def main():
     # direct decision and its argmax; (C) Block-OMP and the refinement, which
     # rebuild their own maps from their own residual.  With two streams, C runs
     # on the capture stream; a second stream (default priority), forked from
-    # and joined back into it, runs B beside the Block-OMP iterations, then,
-    # once the last selection is made, the last fit (the refinement needs only
-    # the selections) and A beside the latency-bound refinement.
+    # and joined back into it, runs B and the maps of A beside the Block-OMP
+    # iterations, then, once the last selection is made, the last fit (the
+    # refinement needs only the selections) and the rest of A beside the
+    # latency-bound refinement.
     side = torch.cuda.Stream(device=dev) if args.streams == 2 else None
 
     def step_two_streams():
@@ -397,6 +398,7 @@ def main():
         with torch.cuda.stream(side):
             gh.direct_decision(radar, dgrid, y, ws=ws, dec=ddec, block=dblock, want_argmax=False)
             gh.argmax(dblock, darg)
+            gh.rd_maps(radar, y, maps)
         bomp.reset()
         for _ in range(BOMP_ITERS - 1):
             bomp.step()
@@ -406,7 +408,6 @@ def main():
         side.wait_event(selected)
         with torch.cuda.stream(side):
             bomp.fit()
-            gh.rd_maps(radar, y, maps)
             gh.decision(radar, grid, maps, interp, dec=dec, block=block, want_argmax=False)
             gh.argmax(block, arg)
         gh.refine(radar, grid, y, bomp.support, theta=theta, ws=rws)

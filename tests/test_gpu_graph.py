@@ -4,8 +4,8 @@ graph: three replays on new frames, copied into the captured input buffer
 between replays, each equal bit for bit to an eager step on the same frame.
 The step is captured on one stream, and on two: a second stream (default
 priority), forked from and joined back into the capture stream, runs the
-direct decision beside the Block-OMP iterations, then the last Block-OMP fit
-and the grid-hopping row beside the refinement.
+direct decision and the maps beside the Block-OMP iterations, then the last
+Block-OMP fit and the grid-hopping sweep and argmax beside the refinement.
 The eager path itself is checked against the FP64 oracle in test_gpu_parity.py.
 """
 import numpy as np
@@ -61,6 +61,7 @@ def test_step_graph_replays_match_eager(cfg, streams):
         with torch.cuda.stream(side):
             gh.direct_decision(radar, dgrid, y, ws=ws, dec=ddec, block=dblock, want_argmax=False)
             gh.argmax(dblock, darg)
+            gh.rd_maps(radar, y, maps)
         bomp.reset()
         for _ in range(2):
             bomp.step()
@@ -70,7 +71,6 @@ def test_step_graph_replays_match_eager(cfg, streams):
         side.wait_event(selected)
         with torch.cuda.stream(side):
             bomp.fit()
-            gh.rd_maps(radar, y, maps)
             gh.decision(radar, grid, maps, gh.BILINEAR, dec=dec, block=block, want_argmax=False)
             gh.argmax(block, arg)
         gh.refine(radar, grid, y, bomp.support, theta=theta, ws=rws)
