@@ -450,6 +450,22 @@ def main():
         torch.cuda.synchronize()
         step_ms = np.array([a.elapsed_time(b) for a, b in per])
 
+        # the same step captured on one stream, timed the same way as `value`
+        one_ms = None
+        if side is not None:
+            g1 = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g1):
+                step(False)
+            for _ in range(args.warmup):
+                g1.replay()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                g1.replay()
+            torch.cuda.synchronize()
+            one_ms = (time.perf_counter() - t1) / args.steps * 1e3
+            del g1
+
         # device-copy bandwidth (read + write bytes of a 256 MiB copy) as the practical HBM ceiling
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -492,6 +508,7 @@ def main():
         err_bf16 = float((ddec_b.double() - ddec.double()).abs().max() / ddec.double().max())
         return {
             "ms_per_step_p10_p50_p90": [float(np.percentile(step_ms, q)) for q in (10, 50, 90)],
+            "ms_per_step_one_stream": one_ms,
             "copy_gbs": copy_gbs,
             "t_gh_sub": t_gh_sub,
             "t_dir_bf16": t_dir_bf16,
@@ -556,6 +573,7 @@ def main():
             "direct_bf16_max_rel_diff_vs_f32": x["err_bf16"],
             "speedup_gh_over_direct_same_subgrid": t_dir / x["t_gh_sub"],
             "ms_per_step_p10_p50_p90": x["ms_per_step_p10_p50_p90"],
+            "ms_per_step_one_stream": x["ms_per_step_one_stream"],
             "copy_gbs": x["copy_gbs"],
             "factored": x["factored"],
         })
