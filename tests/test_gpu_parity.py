@@ -395,13 +395,13 @@ def _resid_maps_view(st, radar, grid_s):
     return st.ws[off:off + nbytes].view(torch.complex64).view(radar.k, radar.nr, radar.nd)
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
-def test_bomp_residual_maps_closed_form(cfg, monkeypatch):
+@pytest.mark.parametrize("cfg,centered", [(1, 1), (2, 1), (1, 0)])
+def test_bomp_residual_maps_closed_form(cfg, centered, monkeypatch):
     """Maps of the residual from the maps of y and the fitted atoms in closed form,
     against the FFT of the residual (per receiver, relative Frobenius <= 1e-5), and
     the same selections as with the FFT of the residual (GH_BOMP_MAPS=fft)."""
-    say(f"bomp residual maps cfg={cfg}")
-    s, r, gr = scene_and_radar(cfg, 0)
+    say(f"bomp residual maps cfg={cfg} centered={centered}")
+    s, r, gr = scene_and_radar(cfg, 0, centered=centered)
     grid = gh.grid_of(s.grid)
     y = to_dev(s.y)
     st = gh.BompState(gr, grid, y, max_support=3)
