@@ -345,6 +345,27 @@ def test_bomp_long_doppler_axis():
         resid_ref = resid_ref.astype(np.complex64)
 
 
+def test_bomp_many_atoms_closed_form_matches_fft(monkeypatch):
+    """Eight iterations (up to seven fitted atoms in the closed-form residual
+    maps) select the same cells and fit the same alpha as the FFT route."""
+    say("bomp eight iterations, closed form against FFT")
+    s, r, gr = scene_and_radar(1, 9, targets=8, snr_db=25.0, k=6)
+    grid = gh.grid_of(s.grid)
+    y = to_dev(s.y)
+    a = gh.BompState(gr, grid, y, max_support=8)
+    for _ in range(8):
+        a.step()
+    torch.cuda.synchronize()
+    monkeypatch.setenv("GH_BOMP_MAPS", "fft")
+    b = gh.BompState(gr, grid, y, max_support=8)
+    for _ in range(8):
+        b.step()
+    torch.cuda.synchronize()
+    assert len(set(a.support.cpu().numpy().tolist())) == 8
+    assert torch.equal(a.support, b.support)
+    assert torch.equal(a.alpha, b.alpha)
+
+
 def test_bomp_fit_cfg2_full_size():
     say("bomp cfg2")
     s, r, gr = scene_and_radar(2)
