@@ -145,6 +145,104 @@ __global__ __launch_bounds__(kThreads) void direct_range_zoom(Geom g, GridP gp, 
     }
 }
 
+// Range zoom with BF16 operands: as below, but the four waves share the frame
+// operand: each 32-sample step of the 64 chirps is staged once in LDS
+// (double-buffered, rows padded to an odd number of 16-byte words so the
+// operand reads do not conflict) instead of being read from L2 by every wave.
+// BF16 products are cheap enough that those L2 reads bound the kernel (71 ->
+// 53 us for the BF16 direct decision of the paper-scale subgrid); in FP32 the
+// staging gains 2 us and its 35 KB of LDS cost more beside other kernels.
+constexpr int kYRows = 16 * kNT;                 // chirps per workgroup
+constexpr int kYRow4 = 32 / 2 + 1;              // float4 per staged row: 32 samples + padding
+
+__global__ __launch_bounds__(kThreads) void direct_range_zoom_bf16(Geom g, GridP gp, const float2* __restrict__ y,
+                                                                  float2* __restrict__ gws) {
+    constexpr bool BF16 = true;
+    __shared__ float4 ytile[2][kYRows][kYRow4];
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15;
+    const int seg = lane >> 4;
+    const int q = blockIdx.z;
+    const int loc0 = (blockIdx.x * kWaves + (threadIdx.x >> 6)) * 16;
+    const int m0 = blockIdx.y * kYRows;
+    const int ms = g.ms, mc = g.mc;
+
+    uint32_t fr = 0;
+    if (loc0 + r < gp.nloc) {
+        const int loc = loc0 + r;
+        const int ix = loc / gp.n[1], iy = loc - ix * gp.n[1];
+        double rr, wx, wy;
+        bistatic(g, q, gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], rr, wx, wy);
+        fr = cycles_to_fixed(g.fr_per_m * rr);
+    }
+    const float2 ratio = expm_fixed(fr);
+
+    f32x4 cre[kNT], cim[kNT];
+#pragma unroll
+    for (int t = 0; t < kNT; ++t) cre[t] = cim[t] = zero4();
+
+    // staging: 64 rows x 16 float4 (32 samples) per step, four float4 per thread
+    const float4* yq4 = reinterpret_cast<const float4*>(y + (size_t)q * mc * ms);
+    constexpr int kPer = kYRows * 16 / kThreads;
+    float4 stage[kPer];
+    auto load_step = [&](int s0) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int idx = threadIdx.x + i * kThreads;
+            const int row = idx >> 4, c4 = idx & 15;
+            const int m = m0 + row, s = s0 + 2 * c4;
+            stage[i] = (m < mc && s < ms) ? yq4[((size_t)m * ms + s) >> 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto store_step = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int idx = threadIdx.x + i * kThreads;
+            ytile[buf][idx >> 4][idx & 15] = stage[i];
+        }
+    };
+    load_step(0);
+    store_step(0);
+    __syncthreads();
+    int buf = 0;
+    for (int s0 = 0; s0 < ms; s0 += 32) {
+        const bool more = s0 + 32 < ms;
+        if (more) load_step(s0 + 32);
+        const int sb = s0 + seg * kRun;
+        const bool live = sb < ms;   // Ms is a power of two >= 8: a run is all in or all out
+        float2 a[kRun];
+        atom_run(fr, (uint32_t)sb, ratio, a);
+        if (!live) {
+#pragma unroll
+            for (int e = 0; e < kRun; ++e) a[e] = make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) {
+            float2 b[kRun];
+            const float4* row = ytile[buf][t * 16 + r] + seg * (kRun / 2);
+#pragma unroll
+            for (int i = 0; i < kRun / 2; ++i) {
+                const float4 v = row[i];
+                b[2 * i] = make_float2(v.x, v.y);
+                b[2 * i + 1] = make_float2(v.z, v.w);
+            }
+            mfma_complex<BF16>(a, b, cre[t], cim[t]);
+        }
+        if (more) store_step(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int t = 0; t < kNT; ++t) {
+        const int m = m0 + t * 16 + r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int loc = loc0 + 4 * seg + e;
+            if (loc < gp.nloc && m < mc) gws[((size_t)q * gp.nloc + loc) * mc + m] = make_float2(cre[t][e], cim[t][e]);
+        }
+    }
+}
+
 // Doppler zoom.  One wave per location; it walks the 16 x 16 tiles of the
 // velocity slab, sums |c_q|^2 over receivers, writes the slab and reduces the
 // block maximum (ties to the lowest index), skipping excluded cells.
@@ -238,7 +336,7 @@ size_t direct_ws_bytes(const Geom& g, const GridP& gp, int /*gemm*/) {
 hipError_t launch_direct_range(const Geom& g, const GridP& gp, const float2* y, int gemm, float2* G, hipStream_t st) {
     const dim3 g1((gp.nloc + 16 * kWaves - 1) / (16 * kWaves), (g.mc + 16 * kNT - 1) / (16 * kNT), g.k);
     if (gemm == GH_GEMM_BF16)
-        hipLaunchKernelGGL(direct_range_zoom<true>, g1, dim3(kThreads), 0, st, g, gp, y, G);
+        hipLaunchKernelGGL(direct_range_zoom_bf16, g1, dim3(kThreads), 0, st, g, gp, y, G);
     else
         hipLaunchKernelGGL(direct_range_zoom<false>, g1, dim3(kThreads), 0, st, g, gp, y, G);
     return hipGetLastError();
@@ -250,7 +348,7 @@ hipError_t launch_direct(const Geom& g, const GridP& gp, const float2* y, int ge
     const dim3 g1((gp.nloc + 16 * kWaves - 1) / (16 * kWaves), (g.mc + 16 * kNT - 1) / (16 * kNT), g.k);
     const dim3 g2((gp.nloc + kWaves - 1) / kWaves);
     if (gemm == GH_GEMM_BF16) {
-        hipLaunchKernelGGL(direct_range_zoom<true>, g1, dim3(kThreads), 0, st, g, gp, y, gws);
+        hipLaunchKernelGGL(direct_range_zoom_bf16, g1, dim3(kThreads), 0, st, g, gp, y, gws);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(direct_doppler_zoom<true>, g2, dim3(kThreads), 0, st, g, gp, gws, dec, block, excl, nexcl);
