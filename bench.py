@@ -15,8 +15,7 @@ synchronisation inside the step:
   5. Newton refinement of the 3 selected cells.
 Grid points evaluated per step: 4 x 16,777,216 (grid hopping) + 1,048,576
 (direct).  `value` is that count divided by the measured step time.  The
-step is captured once in a HIP graph (kernel launches and one device copy;
-no memset) and the timed steps are graph replays.  Rows 1-2, row 3 and rows
+step is captured once in a HIP graph (kernel launches only; no memset) and the timed steps are graph replays.  Rows 1-2, row 3 and rows
 4-5 are three independent chains: by default (`--streams 2`) row 3 and the
 maps of row 1 run on a second stream beside the Block-OMP iterations, and the
 rest of rows 1-2 (after the last Block-OMP fit, which the refinement does not
