@@ -10,22 +10,24 @@ synchronisation inside the step:
      (16,777,216 points), FP32 volume written, block maxima, global argmax;
   3. direct decision on the stride-2 64 x 64 x 16 x 16 subgrid (1,048,576
      points), volume written, block maxima, global argmax;
-  4. Block-OMP, 3 iterations (each: maps of the residual, grid-hopping
-     argmax-only sweep with the support excluded, least-squares fit, residual);
+  4. Block-OMP, 3 iterations (each: maps of the residual (by FFT of the
+     frame in the first, from the maps of the frame and the fitted atoms in
+     closed form after it), grid-hopping argmax-only sweep with the support
+     excluded, least-squares fit, residual);
   5. Newton refinement of the 3 selected cells.
 Grid points evaluated per step: 4 x 16,777,216 (grid hopping) + 1,048,576
 (direct).  `value` is that count divided by the measured step time.  The
-step is captured once in a HIP graph (kernel launches only; no memset) and the timed steps are graph replays.  Rows 1-2, row 3 and rows
-4-5 are three independent chains: by default (`--streams 2`) row 3 and the
-maps of row 1 run on a second stream beside the Block-OMP iterations, and the
-rest of rows 1-2 (after the last Block-OMP fit, which the refinement does not
-need) on that stream beside the refinement; the second stream is forked from
-and joined back into the capture stream.  `--streams 1` captures everything on one stream in the
-order above.  The
-per-row times come from eager one-stream steps with HIP events, and after
-the replays the step's outputs (argmax cells, Block-OMP support and
-coefficients, refined estimates) are compared with those of an eager step
-(`graph_matches_eager`).
+step is captured once in a HIP graph (kernel launches only; no memset) and
+the timed steps are graph replays.  Rows 1-2, row 3 and rows 4-5 are three
+independent chains: by default (`--streams 2`) row 3 and the maps of row 1
+run on a second stream beside the Block-OMP iterations, and the rest of rows
+1-2 (after the last Block-OMP fit, which the refinement does not need) on
+that stream beside the refinement; the second stream is forked from and
+joined back into the capture stream.  `--streams 1` captures everything on
+one stream in the order above.  The per-row times come from eager
+one-stream steps with HIP events, and after the replays the step's outputs
+(argmax cells, Block-OMP support and coefficients, refined estimates) are
+compared with those of an eager step (`graph_matches_eager`).
 
 The roofline object covers the dominant kernel, the grid-hopping sweep of
 step 2, timed with HIP events on the stream it runs on; its algorithmic bytes
