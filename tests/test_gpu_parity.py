@@ -446,6 +446,25 @@ def test_bomp_residual_maps_closed_form(cfg, centered, monkeypatch):
     assert torch.equal(st.alpha, ref.alpha)
 
 
+@pytest.mark.parametrize("pad_r,pad_d,centered", [(2, 8, 0), (8, 2, 1), (1, 1, 1)])
+def test_bomp_residual_maps_other_paddings(pad_r, pad_d, centered):
+    """The closed-form residual maps with unequal, large and no zero padding,
+    against the FFT of the residual (relative Frobenius <= 1e-5)."""
+    say(f"bomp residual maps pad_r={pad_r} pad_d={pad_d} centered={centered}")
+    s = sc.make_scene(1, 3, targets=3, snr_db=20.0, centered=centered)
+    gr = gh.Radar(s.f0, s.bw, s.tc, s.ms, s.mc, s.tx, s.rx, pad_r, pad_d, centered, s.c)
+    st = gh.BompState(gr, gh.grid_of(s.grid), to_dev(s.y), max_support=3)
+    st.step()
+    st.step()
+    st.select()
+    torch.cuda.synchronize()
+    z_closed = _resid_maps_view(st, gr, s.grid).cpu().numpy().astype(np.complex128)
+    z_fft = gh.rd_maps(gr, st.resid).cpu().numpy().astype(np.complex128)
+    for q in range(gr.k):
+        err = np.linalg.norm(z_closed[q] - z_fft[q]) / np.linalg.norm(z_fft[q])
+        assert err <= 1e-5, (q, err)
+
+
 # ---------------------------------------------------------------- refinement
 
 @pytest.mark.parametrize("kernel", ["cluster", "single"])
