@@ -10,7 +10,11 @@
 // The right-hand side is spread over workgroups of 8 chirps (separable atoms,
 // FP32 products over a chirp, FP64 from there on) and summed in a fixed order;
 // the residual's workgroups each solve the small system themselves (identical
-// inputs, identical order, so identical alpha), which saves a launch.
+// inputs, identical order, so identical alpha), which saves a launch.  They
+// also leave the fitted atoms' maps (alpha_t R_t[i] and D_t[l], closed-form
+// Dirichlet sums along range and Doppler) for the next selection, whose maps
+// of the residual are then the maps of Y minus sum_t alpha_t R_t[i] D_t[l]
+// (the maps are linear in the frame).
 #include "gh_internal.h"
 
 namespace gh {
