@@ -16,6 +16,7 @@
 // of the residual are then the maps of Y minus sum_t alpha_t R_t[i] D_t[l]
 // (the maps are linear in the frame).
 #include "gh_internal.h"
+#include "lane_sum.h"
 
 namespace gh {
 namespace {
@@ -104,12 +105,9 @@ __global__ __launch_bounds__(kThreads) void bomp_rhs_kernel(Geom g, GridP gp, co
             const float2 d = ed[t0 + t][row];
             double pr = (double)re * d.x - (double)im * d.y;
             double pi = (double)re * d.y + (double)im * d.x;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                pr += __shfl_xor(pr, off, 64);
-                pi += __shfl_xor(pi, off, 64);
-            }
-            if ((tid & 63) == 0) red[tid >> 6][t0 + t] = make_double2(pr, pi);
+            double pv[2] = {pr, pi};
+            group_sum_to_first(pv, 64);   // the wave's sum in lane 0
+            if ((tid & 63) == 0) red[tid >> 6][t0 + t] = make_double2(pv[0], pv[1]);
         }
     }
     __syncthreads();
