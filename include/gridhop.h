@@ -195,8 +195,10 @@ size_t gh_bomp_workspace_bytes(const gh_radar *radar, const gh_grid *grid, int32
  * d_maps: complex64 map buffer [K][N_r][N_d] (grid hopping: written at
  * n_support == 0 and read by the later iterations of the run, so the caller
  * passes the same buffer, unchanged, throughout; may be NULL when
- * use_direct == 1).  d_ws carries the fitted atoms' maps from one
- * iteration to the next: pass the same workspace throughout a run.
+ * use_direct == 1).  d_ws carries from one iteration to the next the
+ * fitted atoms' maps and a counter of the grid maximum that the iteration at
+ * n_support == 0 zeroes and the later ones leave at zero: a run starts at
+ * n_support == 0 and passes the same workspace throughout.
  * d_support: int64 [max_support], in/out.
  * 0 <= n_support < max_support <= GH_MAX_SUPPORT.  d_selected: gh_peak [1]
  * (NULL: not written), the selected maximum.  Everything stays on the

@@ -291,7 +291,15 @@ size_t gh_bomp_workspace_bytes(const gh_radar* radar, const gh_grid* grid, int32
         b += align256(gh::direct_ws_bytes(g, gp, gemm_dtype));
     else
         b += align256((size_t)g.k * g.nr * g.nd * sizeof(float2));   // maps of the residual
-    return b;
+    return b + align256(gh::peak_split_ws_bytes());                   // the selection's split maximum
+}
+
+// Start of the split maximum's part of a Block-OMP workspace.
+static char* bomp_split_ws(const gh::Geom& g, const gh::GridP& gp, int32_t use_direct, int32_t gemm_dtype, char* ws) {
+    ws += align256((size_t)gp.nloc * sizeof(gh_peak)) + align256(gh::bomp_fit_ws_bytes(g)) +
+          align256(gh::bomp_atom_vec_bytes(g));
+    return ws + (use_direct ? align256(gh::direct_ws_bytes(g, gp, gemm_dtype))
+                            : align256((size_t)g.k * g.nr * g.nd * sizeof(float2)));
 }
 
 // Shared checks of the Block-OMP entry points; sets g, gp.
@@ -311,13 +319,16 @@ static int bomp_common(const gh_radar* radar, const gh_grid* grid, int32_t use_d
 // n_support == 0; later, the maps of the residual are built in the workspace
 // from them and the atom maps the previous fit left in the workspace, or by
 // the FFT of the residual where the atoms' Doppler table does not fit (or
-// with GH_BOMP_MAPS=fft, diagnostics).
+// with GH_BOMP_MAPS=fft, diagnostics).  The maximum over the grid is taken by
+// one workgroup at n_support == 0, which also zeroes the ticket counter of the
+// split maximum that the later selections use (and leave at zero).
 // Arguments already checked.
 static hipError_t bomp_select_launch(const gh::Geom& g, const gh::GridP& gp, const void* d_y, const void* d_resid,
                                      void* d_maps, int32_t use_direct, int32_t interp, int32_t gemm_dtype,
                                      int64_t* d_support, int32_t n_support, gh_peak* d_selected, char* ws,
                                      hipStream_t st) {
     const float2* src = (const float2*)(n_support == 0 ? d_y : d_resid);
+    char* split_ws = bomp_split_ws(g, gp, use_direct, gemm_dtype, ws);
     gh_peak* block = (gh_peak*)ws;
     ws += align256((size_t)gp.nloc * sizeof(gh_peak));
     ws += align256(gh::bomp_fit_ws_bytes(g));
@@ -341,8 +352,10 @@ static hipError_t bomp_select_launch(const gh::Geom& g, const gh::GridP& gp, con
         if (e == hipSuccess)
             e = gh::launch_gh_sweep(g, gp, rmaps, GH_MAP_C64, interp, nullptr, block, d_support, n_support, st);
     }
-    if (e == hipSuccess) e = gh::launch_peak_final(block, gp.nloc, d_selected, d_support + n_support, st);
-    return e;
+    if (e != hipSuccess) return e;
+    if (n_support == 0)
+        return gh::launch_peak_final(block, gp.nloc, d_selected, d_support + n_support, st, (unsigned*)split_ws);
+    return gh::launch_peak_final_split(block, gp.nloc, d_selected, d_support + n_support, split_ws, st);
 }
 
 static hipError_t bomp_fit_launch(const gh::Geom& g, const gh::GridP& gp, const void* d_y, void* d_resid,

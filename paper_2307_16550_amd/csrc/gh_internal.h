@@ -310,8 +310,16 @@ hipError_t launch_gh_sweep_columns(const Geom& g, const GridP& gp, int lpb, int 
                                    const void* maps, int map_dtype, int interp, float* dec, gh_peak* block,
                                    const int64_t* excl, int nexcl, hipStream_t st);
 
+// Global maximum of nblock block maxima (one workgroup); also zeroes *clear
+// when it is not null.
 hipError_t launch_peak_final(const gh_peak* block, int nblock, gh_peak* out, int64_t* support_slot,
-                             hipStream_t st);
+                             hipStream_t st, unsigned* clear = nullptr);
+// The same maximum split over several workgroups, the last of which merges
+// their shares.  ws: peak_split_ws_bytes() of device memory whose first word
+// (a ticket counter) is zero; the launch leaves it zero.
+size_t peak_split_ws_bytes();
+hipError_t launch_peak_final_split(const gh_peak* block, int nblock, gh_peak* out, int64_t* support_slot, void* ws,
+                                   hipStream_t st);
 
 size_t direct_ws_bytes(const Geom& g, const GridP& gp, int gemm);
 hipError_t launch_direct(const Geom& g, const GridP& gp, const float2* y, int gemm, void* ws, float* dec,

@@ -174,7 +174,8 @@ __global__ __launch_bounds__(kThreads) void gh_sweep_kernel(Geom g, GridP gp, co
 
 // Global maximum over per-location peaks (one workgroup).
 __global__ __launch_bounds__(1024) void peak_final_kernel(const gh_peak* __restrict__ blk, int n,
-                                                         gh_peak* __restrict__ out, int64_t* __restrict__ slot) {
+                                                         gh_peak* __restrict__ out, int64_t* __restrict__ slot,
+                                                         unsigned* __restrict__ clear) {
     __shared__ float red_v[16];
     __shared__ long long red_i[16];
     float bv;
@@ -189,6 +190,72 @@ __global__ __launch_bounds__(1024) void peak_final_kernel(const gh_peak* __restr
             *out = p;
         }
         if (slot) *slot = bi;
+        if (clear) *clear = 0u;
+    }
+}
+
+// Global maximum over per-location peaks, split over up to kSplitWgs
+// workgroups: each reduces a contiguous share, stores its result in part[]
+// and takes a ticket from `done`; the workgroup holding the last ticket merges
+// the shares (ties to the lowest index, as in peak_final_kernel), writes the
+// result and sets `done` back to zero.  `done` must be zero when the launch
+// starts.  A few release fences replace the latency of one workgroup reading
+// every peak.
+constexpr int kSplitWgs = 64;
+constexpr int kSplitThreads = 256;
+
+__global__ __launch_bounds__(kSplitThreads) void peak_final_split_kernel(const gh_peak* __restrict__ blk, int n,
+                                                                       int share, gh_peak* __restrict__ out,
+                                                                       int64_t* __restrict__ slot,
+                                                                       unsigned* __restrict__ done,
+                                                                       gh_peak* __restrict__ part) {
+    __shared__ float red_v[kSplitThreads / 64];
+    __shared__ long long red_i[kSplitThreads / 64];
+    __shared__ int last;
+    const int b0 = blockIdx.x * share;
+    const int len = min(share, n - b0);
+    float bv;
+    long long bi;
+    reduce_block_peaks(blk + b0, len, bv, bi, red_v, red_i);
+    if (threadIdx.x == 0) {
+        gh_peak p;
+        p.value = bv;
+        p.reserved = 0;
+        p.index = bi;
+        part[blockIdx.x] = p;
+        __threadfence();
+        last = atomicAdd(done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last || threadIdx.x >= 64) return;
+    // every other workgroup stored its share before taking its ticket
+    __threadfence();
+    const int t = threadIdx.x;
+    bv = -INFINITY;
+    bi = 0x7fffffffffffffffLL;
+    if (t < (int)gridDim.x) {
+        const gh_peak p = part[t];
+        bv = p.value;
+        bi = p.index;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        const float v2 = __shfl_xor(bv, off, 64);
+        const long long i2 = __shfl_xor(bi, off, 64);
+        if (v2 > bv || (v2 == bv && i2 < bi)) {
+            bv = v2;
+            bi = i2;
+        }
+    }
+    if (t == 0) {
+        if (out) {
+            gh_peak p;
+            p.value = bv;
+            p.reserved = 0;
+            p.index = bi;
+            *out = p;
+        }
+        if (slot) *slot = bi;
+        *done = 0u;
     }
 }
 
@@ -229,9 +296,26 @@ hipError_t launch_gh_sweep(const Geom& g, const GridP& gp, const void* maps, int
     return hipGetLastError();
 }
 
-hipError_t launch_peak_final(const gh_peak* block, int nblock, gh_peak* out, int64_t* support_slot,
-                             hipStream_t st) {
-    hipLaunchKernelGGL(peak_final_kernel, dim3(1), dim3(1024), 0, st, block, nblock, out, support_slot);
+hipError_t launch_peak_final(const gh_peak* block, int nblock, gh_peak* out, int64_t* support_slot, hipStream_t st,
+                             unsigned* clear) {
+    hipLaunchKernelGGL(peak_final_kernel, dim3(1), dim3(1024), 0, st, block, nblock, out, support_slot, clear);
+    return hipGetLastError();
+}
+
+size_t peak_split_ws_bytes() { return 256 + kSplitWgs * sizeof(gh_peak); }
+
+hipError_t launch_peak_final_split(const gh_peak* block, int nblock, gh_peak* out, int64_t* support_slot, void* ws,
+                                   hipStream_t st) {
+    // shares of 16 peaks per thread (one load batch), 4 for small inputs, at most kSplitWgs shares
+    const int64_t n = nblock;
+    int64_t share = 16 * kSplitThreads;
+    if ((n + share - 1) / share < kSplitWgs / 4) share = 4 * kSplitThreads;
+    if ((n + share - 1) / share > kSplitWgs) share = (n + kSplitWgs - 1) / kSplitWgs;
+    const int nwg = (int)((n + share - 1) / share);
+    unsigned* done = static_cast<unsigned*>(ws);
+    gh_peak* part = reinterpret_cast<gh_peak*>(static_cast<char*>(ws) + 256);
+    hipLaunchKernelGGL(peak_final_split_kernel, dim3(nwg), dim3(kSplitThreads), 0, st, block, nblock, (int)share,
+                       out, support_slot, done, part);
     return hipGetLastError();
 }
 

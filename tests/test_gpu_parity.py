@@ -465,27 +465,35 @@ def test_bomp_residual_maps_other_paddings(pad_r, pad_d, centered):
         assert err <= 1e-5, (q, err)
 
 
-@pytest.mark.parametrize("n", [(32, 32, 8, 8), (7, 5, 8, 8), (1, 1, 8, 8), (1, 3, 16, 4), (9, 9, 6, 6)])
+@pytest.mark.parametrize("n", [(32, 32, 8, 8), (7, 5, 8, 8), (1, 1, 8, 8), (1, 3, 16, 4), (9, 9, 6, 6),
+                               (257, 256, 1, 2), (520, 512, 1, 2)])
 def test_bomp_selection_is_max_of_block_maxima(n):
-    """Every Block-OMP selection (one location, a ragged last sweep workgroup,
-    and the generic sweep for a vy axis that is not a power of two) equals the
-    host maximum of the block maxima the sweep left at the start of the
-    workspace: value and index bit for bit, ties to the lowest index, and the
-    index lands in the support."""
+    """Every Block-OMP selection equals the host maximum of the block maxima the
+    sweep left at the start of the workspace (value and index bit for bit, ties
+    to the lowest index) and lands in the support; the ticket counter of the
+    split maximum (after the residual maps) is zero after every selection.
+    Shapes: one location, a ragged last sweep workgroup, the generic sweep for
+    a vy axis that is not a power of two, and enough locations for 17 and for
+    the cap of 64 workgroups of the split maximum."""
     say(f"bomp selection vs block maxima n={n}")
     s, r, gr = scene_and_radar(1, 2)
     g = sc.full_grid(n)
     nloc = n[0] * n[1]
+    a256 = lambda v: (v + 255) // 256 * 256
+    off = (a256(nloc * 16) + a256(gr.k * (gr.mc // 8) * gh.MAX_SUPPORT * 16)
+           + a256(gr.k * gh.MAX_SUPPORT * (gr.nr + gr.nd) * 8) + a256(gr.k * gr.nr * gr.nd * 8))
     st = gh.BompState(gr, gh.grid_of(g), to_dev(s.y), max_support=4)
+    assert st.ws.numel() == off + a256(256 + 64 * 16)
     for it in range(4):
         st.select()
         torch.cuda.synchronize()
         vals, idx = gh.decode_peaks(st.ws[:nloc * 16].view(torch.int64).view(nloc, 2))
-        best = max(range(nloc), key=lambda i: (vals[i], -idx[i]))
+        best = int(np.lexsort((idx, -vals.astype(np.float64)))[0])
         sv, si = gh.decode_peaks(st.selected)
         say(f"  iteration {it}: selected {int(si[0])} value {float(sv[0]):.9g}")
         assert int(si[0]) == int(idx[best]) and float(sv[0]) == float(vals[best]), (it, int(si[0]), int(idx[best]))
         assert int(st.support[it]) == int(idx[best])
+        assert int(st.ws[off:off + 4].view(torch.int32)[0]) == 0
         st.fit()
 
 
