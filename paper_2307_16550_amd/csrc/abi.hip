@@ -319,9 +319,10 @@ static int bomp_common(const gh_radar* radar, const gh_grid* grid, int32_t use_d
 // n_support == 0; later, the maps of the residual are built in the workspace
 // from them and the atom maps the previous fit left in the workspace, or by
 // the FFT of the residual where the atoms' Doppler table does not fit (or
-// with GH_BOMP_MAPS=fft, diagnostics).  The maximum over the grid is taken by
-// one workgroup at n_support == 0, which also zeroes the ticket counter of the
-// split maximum that the later selections use (and leave at zero).
+// with GH_BOMP_MAPS=fft, diagnostics).  The maximum over the grid is split
+// over several workgroups, with a ticket counter in the workspace that each
+// such launch leaves at zero; at n_support == 0 the Doppler pass of the maps
+// (grid hopping) or a one-workgroup maximum (direct) zeroes it first.
 // Arguments already checked.
 static hipError_t bomp_select_launch(const gh::Geom& g, const gh::GridP& gp, const void* d_y, const void* d_resid,
                                      void* d_maps, int32_t use_direct, int32_t interp, int32_t gemm_dtype,
@@ -338,7 +339,7 @@ static hipError_t bomp_select_launch(const gh::Geom& g, const gh::GridP& gp, con
     if (use_direct) {
         e = gh::launch_direct(g, gp, src, gemm_dtype, ws, nullptr, block, d_support, n_support, st);
     } else if (n_support == 0) {
-        e = gh::launch_rd_maps(g, src, d_maps, GH_MAP_C64, st);
+        e = gh::launch_rd_maps(g, src, d_maps, GH_MAP_C64, st, (unsigned*)split_ws);
         if (e == hipSuccess)
             e = gh::launch_gh_sweep(g, gp, d_maps, GH_MAP_C64, interp, nullptr, block, d_support, n_support, st);
     } else {
@@ -353,7 +354,7 @@ static hipError_t bomp_select_launch(const gh::Geom& g, const gh::GridP& gp, con
             e = gh::launch_gh_sweep(g, gp, rmaps, GH_MAP_C64, interp, nullptr, block, d_support, n_support, st);
     }
     if (e != hipSuccess) return e;
-    if (n_support == 0)
+    if (n_support == 0 && use_direct)
         return gh::launch_peak_final(block, gp.nloc, d_selected, d_support + n_support, st, (unsigned*)split_ws);
     return gh::launch_peak_final_split(block, gp.nloc, d_selected, d_support + n_support, split_ws, st);
 }

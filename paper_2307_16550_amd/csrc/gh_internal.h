@@ -266,7 +266,9 @@ struct FrameDesc {
 
 // ---- host launchers (return hipError_t of the launches) --------------------
 
-hipError_t launch_rd_maps(const Geom& g, const float2* y, void* maps, int map_dtype, hipStream_t st);
+// clear: optional counter zeroed by the Doppler pass (see launch_peak_final_split).
+hipError_t launch_rd_maps(const Geom& g, const float2* y, void* maps, int map_dtype, hipStream_t st,
+                          unsigned* clear = nullptr);
 
 // Work decomposition of the map passes: nch chirps per range workgroup (LDS
 // lds1), nrow range rows per Doppler workgroup (LDS lds2, pre-twiddles in LDS

@@ -228,9 +228,13 @@ __device__ __forceinline__ void doppler_unit(const Geom& g, int nrow, int pre_ld
     }
 }
 
+// `clear`, when not null, is a caller's counter that the first workgroup sets
+// to zero (the Block-OMP selection's split maximum, which runs after the maps).
 template <int DT>
-__global__ __launch_bounds__(kThreads) void doppler_pass(Geom g, int nrow, int pre_lds, char* __restrict__ maps) {
+__global__ __launch_bounds__(kThreads) void doppler_pass(Geom g, int nrow, int pre_lds, char* __restrict__ maps,
+                                                         unsigned* __restrict__ clear) {
     extern __shared__ float2 lds[];
+    if (clear && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *clear = 0u;
     doppler_unit<DT>(g, nrow, pre_lds, maps, blockIdx.x * nrow, blockIdx.y, lds);
 }
 
@@ -349,7 +353,8 @@ hipError_t launch_range_spectra(const Geom& g, const float2* y, float2* spectra,
     return hipGetLastError();
 }
 
-hipError_t launch_rd_maps(const Geom& g, const float2* y, void* maps_v, int map_dtype, hipStream_t st) {
+hipError_t launch_rd_maps(const Geom& g, const float2* y, void* maps_v, int map_dtype, hipStream_t st,
+                          unsigned* clear) {
     char* maps = static_cast<char*>(maps_v);
     const size_t row_bytes = (size_t)g.nd * map_elem_bytes(map_dtype);
     int nch, nrow, pre_lds;
@@ -360,11 +365,14 @@ hipError_t launch_rd_maps(const Geom& g, const float2* y, void* maps_v, int map_
     if (e != hipSuccess) return e;
     const dim3 grid2(g.nr / nrow, g.k);
     if (map_dtype == GH_MAP_F16)
-        hipLaunchKernelGGL(doppler_pass<GH_MAP_F16>, grid2, dim3(kThreads), lds2, st, g, nrow, pre_lds, maps);
+        hipLaunchKernelGGL(doppler_pass<GH_MAP_F16>, grid2, dim3(kThreads), lds2, st, g, nrow, pre_lds, maps,
+                           clear);
     else if (map_dtype == GH_MAP_BF16)
-        hipLaunchKernelGGL(doppler_pass<GH_MAP_BF16>, grid2, dim3(kThreads), lds2, st, g, nrow, pre_lds, maps);
+        hipLaunchKernelGGL(doppler_pass<GH_MAP_BF16>, grid2, dim3(kThreads), lds2, st, g, nrow, pre_lds, maps,
+                           clear);
     else
-        hipLaunchKernelGGL(doppler_pass<GH_MAP_C64>, grid2, dim3(kThreads), lds2, st, g, nrow, pre_lds, maps);
+        hipLaunchKernelGGL(doppler_pass<GH_MAP_C64>, grid2, dim3(kThreads), lds2, st, g, nrow, pre_lds, maps,
+                           clear);
     return hipGetLastError();
 }
 
