@@ -317,7 +317,8 @@ static int bomp_common(const gh_radar* radar, const gh_grid* grid, int32_t use_d
 // Decision on the residual (y itself at n_support == 0) and selection into
 // support[n_support].  Grid hopping: the maps of y go to d_maps at
 // n_support == 0; later, the maps of the residual are built in the workspace
-// from them and the atom maps the previous fit left in the workspace, or by
+// (the range rows the sweep reads) from them and the atom maps the previous
+// fit left in the workspace, or by
 // the FFT of the residual where the atoms' Doppler table does not fit (or
 // with GH_BOMP_MAPS=fft, diagnostics).  The maximum over the grid is split
 // over several workgroups, with a ticket counter in the workspace that each
@@ -347,7 +348,7 @@ static hipError_t bomp_select_launch(const gh::Geom& g, const gh::GridP& gp, con
         const bool fft_only = mode && strcmp(mode, "fft") == 0;
         float2* rmaps = (float2*)ws;
         if (!fft_only && gh::bomp_resid_maps_ok(g, n_support))
-            e = gh::launch_bomp_resid_maps(g, (const float2*)d_maps, atom_vec, n_support, rmaps, st);
+            e = gh::launch_bomp_resid_maps(g, gp, (const float2*)d_maps, atom_vec, n_support, rmaps, st);
         else
             e = gh::launch_rd_maps(g, src, rmaps, GH_MAP_C64, st);
         if (e == hipSuccess)

@@ -260,15 +260,28 @@ __global__ __launch_bounds__(kThreads) void bomp_fit_residual_kernel(Geom g, Gri
 constexpr int kResRows = 8;          // map rows per workgroup of the residual maps
 constexpr int kResTable = 4096;      // Doppler-axis values (atoms x N_d) held in LDS
 
+// Row groups of kResRows map rows that each receiver's residual maps need:
+// groups first[q], first[q] + 1, ... (modulo N_r / kResRows), count[q] of them.
+struct ResRowGroups {
+    int first[kMaxRx];
+    int count[kMaxRx];
+};
+
 // Z_res[q][i][l] = Z_y[q][i][l] - sum_t (alpha_t R_t)[i] D_t[l], where the maps of
 // the atom A(theta_t) = b(f_d) (x) a(f_r) are R_t[i] D_t[l] (the single-axis tone
-// values above, written by the fit with alpha applied).  Grid (N_r / kResRows, K).
-__global__ __launch_bounds__(kThreads) void bomp_resid_maps_kernel(Geom g, const float2* __restrict__ maps_y,
+// values above, written by the fit with alpha applied), on the row groups of
+// `rg`.  Grid (max_q rg.count[q], K).
+__global__ __launch_bounds__(kThreads) void bomp_resid_maps_kernel(Geom g, ResRowGroups rg,
+                                                                  const float2* __restrict__ maps_y,
                                                                   const float2* __restrict__ atom_vec, int nsel,
                                                                   float2* __restrict__ out) {
     __shared__ float2 dv[kResTable];
     __shared__ float2 cr[kMaxSupport][kResRows];
-    const int q = blockIdx.y, i0 = blockIdx.x * kResRows, tid = threadIdx.x;
+    const int q = blockIdx.y, tid = threadIdx.x;
+    if ((int)blockIdx.x >= rg.count[q]) return;
+    const int ngroups = g.nr / kResRows;
+    const int gi = (rg.first[q] + (int)blockIdx.x) % ngroups;
+    const int i0 = gi * kResRows;
     const int nd = g.nd, len = g.nr + g.nd;
     const float2* av = atom_vec + (size_t)q * kMaxSupport * len;
     for (int e = tid; e < nsel * nd; e += kThreads) {
@@ -301,10 +314,54 @@ bool bomp_resid_maps_ok(const Geom& g, int nsel) {
 
 size_t bomp_atom_vec_bytes(const Geom& g) { return (size_t)g.k * kMaxSupport * (g.nr + g.nd) * sizeof(float2); }
 
-hipError_t launch_bomp_resid_maps(const Geom& g, const float2* maps_y, const float2* atom_vec, int nsel, float2* out,
-                                  hipStream_t st) {
-    hipLaunchKernelGGL(bomp_resid_maps_kernel, dim3(g.nr / kResRows, g.k), dim3(kThreads), 0, st, g, maps_y, atom_vec,
-                       nsel, out);
+// Map rows the sweep can read for receiver q over the grid's locations: the
+// taps floor(t_r) - 1 .. floor(t_r) + 2 (bicubic; bilinear reads a subset) of
+// t_r = kr R for R between a lower bound of the bistatic range over the grid's
+// (x, y) rectangle (the larger of the baseline and the sum of the two
+// distances to the rectangle) and its maximum, which lies at a corner because
+// R is convex; one more row on each side covers rounding.  As row groups.
+static void touched_row_groups(const Geom& g, const GridP& gp, int q, int& first, int& count) {
+    const int ngroups = g.nr / kResRows;
+    const double x0 = gp.lo[0], x1 = gp.lo[0] + (gp.n[0] - 1) * gp.step[0];
+    const double y0 = gp.lo[1], y1 = gp.lo[1] + (gp.n[1] - 1) * gp.step[1];
+    auto to_rect = [&](const double* p) {
+        const double dx = fmax(fmax(x0 - p[0], p[0] - x1), 0.0), dy = fmax(fmax(y0 - p[1], p[1] - y1), 0.0);
+        return sqrt(dx * dx + dy * dy);
+    };
+    auto dist = [](double ax, double ay, const double* p) {
+        return sqrt((ax - p[0]) * (ax - p[0]) + (ay - p[1]) * (ay - p[1]));
+    };
+    const double* tx = g.tx;
+    const double* rx = g.rx[q];
+    double rmax = 0.0;
+    for (int c = 0; c < 4; ++c) {
+        const double cx = (c & 1) ? x1 : x0, cy = (c & 2) ? y1 : y0;
+        rmax = fmax(rmax, dist(cx, cy, tx) + dist(cx, cy, rx));
+    }
+    const double rmin = fmax(dist(tx[0], tx[1], rx), to_rect(tx) + to_rect(rx));
+    const double lo = floor(g.kr * rmin) - 2.0, hi = floor(g.kr * rmax) + 3.0;
+    if (!(hi - lo + 1.0 < (double)g.nr)) {
+        first = 0;
+        count = ngroups;
+        return;
+    }
+    const long long l = (long long)lo, h = (long long)hi;
+    const long long gl = (l >= 0 ? l : l - kResRows + 1) / kResRows;   // floor division
+    const long long gh = (h >= 0 ? h : h - kResRows + 1) / kResRows;
+    count = (int)(gh - gl + 1 < ngroups ? gh - gl + 1 : ngroups);
+    first = (int)(((gl % ngroups) + ngroups) % ngroups);
+}
+
+hipError_t launch_bomp_resid_maps(const Geom& g, const GridP& gp, const float2* maps_y, const float2* atom_vec,
+                                  int nsel, float2* out, hipStream_t st) {
+    ResRowGroups rg{};
+    int width = 0;
+    for (int q = 0; q < g.k; ++q) {
+        touched_row_groups(g, gp, q, rg.first[q], rg.count[q]);
+        if (rg.count[q] > width) width = rg.count[q];
+    }
+    hipLaunchKernelGGL(bomp_resid_maps_kernel, dim3(width, g.k), dim3(kThreads), 0, st, g, rg, maps_y, atom_vec, nsel,
+                       out);
     return hipGetLastError();
 }
 

@@ -337,10 +337,12 @@ hipError_t launch_bomp_fit(const Geom& g, const GridP& gp, const float2* y, floa
                            hipStream_t st);
 // Maps of the residual Y - sum_t alpha_t A(theta_t) from the maps of Y by
 // linearity, with the atom vectors of the last fit.  Applies while nsel * N_d
-// fits the kernel's table (bomp_resid_maps_ok).
+// fits the kernel's table (bomp_resid_maps_ok).  Only the range rows that a
+// sweep over the grid gp can read (a bound from its bistatic range span) are
+// written; the other rows of `out` keep their contents.
 bool bomp_resid_maps_ok(const Geom& g, int nsel);
-hipError_t launch_bomp_resid_maps(const Geom& g, const float2* maps_y, const float2* atom_vec, int nsel, float2* out,
-                                  hipStream_t st);
+hipError_t launch_bomp_resid_maps(const Geom& g, const GridP& gp, const float2* maps_y, const float2* atom_vec,
+                                  int nsel, float2* out, hipStream_t st);
 
 size_t refine_ws_bytes(const Geom& g, int ncells);
 hipError_t launch_refine(const Geom& g, const GridP& gp, const float2* y, const int64_t* cells, int ncells,
