@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kThreads) void bomp_fit_residual_kernel(Geom g, Gri
     }
 }
 
-constexpr int kResRows = 4;          // map rows per workgroup of the residual maps
+constexpr int kResRows = 2;          // map rows per workgroup of the residual maps
 constexpr int kResTable = 4096;      // Doppler-axis values (atoms x N_d) held in LDS
 
 // Row groups of kResRows map rows that each receiver's residual maps need:
