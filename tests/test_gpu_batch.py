@@ -20,6 +20,7 @@ import torch
 from oracle import gh as ogh, maps as omaps, peaks as opeaks, radar as ord_
 from paper_2307_16550_amd import gridhop as gh
 from paper_2307_16550_amd import scene as sc
+import _golden
 
 pytestmark = pytest.mark.gpu
 
@@ -250,8 +251,9 @@ def test_batching_workload_bicubic_against_single_frames():
 def test_batching_workload():
     """The batching workload: 64 seeded frames of mixed shapes (K 3..8, Ms 128/256,
     Mc 64/128, grids 64^2..192^2 x 16^2..32^2), autotuned, then replayed as a graph.
-    Every frame's argmax against the single-frame path; oracle checks at sampled
-    grid points of four frames."""
+    Every frame's argmax against the single-frame path and against the FP64
+    oracle's maximum over the frame's whole grid (golden file); oracle checks at
+    sampled grid points of four frames."""
     scenes = sc.make_batch()
     b = gh.Batch.from_scenes(scenes, gh.BILINEAR)
     info = b.info()
@@ -279,6 +281,19 @@ def test_batching_workload():
         else:
             assert am[0][i] == v1[0] or abs(am[0][i] - v1[0]) <= DEC_TOL * v1[0]
     say(f"argmax: {64 - near} identical, {near} near ties")
+    # every frame's argmax against the FP64 oracle's maximum over that frame's whole grid
+    gold = _golden.load("batch_bilinear")["frames"]
+    near_oracle = 0
+    for i, s in enumerate(scenes):
+        g = gold[i]
+        assert g["frame_sha256"] == _golden.frame_sha(s.y), f"golden frame {i}: the generator draws another frame"
+        r = ord_.radar_from_scene(s)
+        at = lambda j, s=s, r=r: float(ogh.gh_points(omaps.rd_maps(s.y, r.pad_r, r.pad_d, r.centered), r,
+                                                     *ord_.grid_point(s.grid, j), gh.BILINEAR))
+        near_oracle += _golden.check(int(am[1][i]), g, at, TIE_TOL, f"batch frame {i}")
+        if int(am[1][i]) == g["argmax"]:
+            assert abs(float(am[0][i]) - g["value"]) <= DEC_TOL * g["value"], i
+    say(f"argmax against the oracle: {64 - near_oracle} identical, {near_oracle} near ties")
     # oracle at sampled grid points of four frames (block maxima carry the decision values)
     rng = np.random.default_rng(5)
     for i in (0, 17, 40, 63):
