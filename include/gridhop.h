@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define GH_ABI_VERSION 1
+#define GH_ABI_VERSION 2
 #define GH_MAX_RX 16
 #define GH_MAX_SUPPORT 32
 
@@ -234,22 +234,28 @@ int gh_bomp_fit(const gh_radar *radar, const gh_grid *grid, const void *d_y, voi
 size_t gh_refine_workspace_bytes(const gh_radar *radar, const gh_grid *grid, int32_t n_cells);
 
 /* Off-grid refinement of the direct decision (not in the paper): starting at
- * each cell (int64 linear grid index, device), maximise D_dir over continuous
- * (x, y, vx, vy) within one grid step per axis by Newton ascent with analytic
- * gradient and Hessian (eigenvalues replaced by -|lambda|, step halving until
- * the decision does not decrease, at most 16 candidates, clamping to the box).
- * Stops when every step component, or the accepted move, is below 1e-7 grid
- * steps, or after max_iter (1..100) iterations.  An axis with one grid point
- * is held.  d_ws: workspace of gh_refine_workspace_bytes() (barrier counters
+ * each cell (int64 linear grid index, device), the converged local maximum of
+ * D_dir over continuous (x, y, vx, vy) within one grid step per axis (the box
+ * around the cell), by projected Newton ascent with analytic gradient and
+ * Hessian: a coordinate next to a face of the box whose gradient points
+ * outwards is put on that face, the others take the Newton step of the
+ * problem restricted to them (eigenvalues replaced by -|lambda|); the step is
+ * halved until the decision does not decrease (at most 16 candidates).  Stops
+ * when the projected step, or the accepted move, is below 1e-7 grid steps in
+ * every coordinate (KKT on the box), or after max_iter (1..100) iterations.
+ * An axis with one grid point is held.  d_ws: workspace of
+ * gh_refine_workspace_bytes() (barrier counters
  * and partial moments; its contents need no initialisation; may be NULL when
- * n_cells == 0, which enqueues nothing).
+ * n_cells == 0, which enqueues nothing and leaves d_status unwritten).
  * d_theta: double [n_cells][4] out; NaN marks a cell whose cooperating
- * workgroups failed to meet within a bounded wait (about a second; possible
+ * workgroups failed to meet within a bounded wait (at least 0.2 s; possible
  * only when other work holds the device's compute units for that long).
+ * d_status: int32 [1] out (NULL: not written), the number of such NaN cells
+ * (0 when every estimate is valid); read it after synchronising the stream.
  * Moments accumulate in FP32 per chirp and FP64 beyond; fixed-point phases. */
 int gh_refine(const gh_radar *radar, const gh_grid *grid, const void *d_y, const int64_t *d_cells,
               int32_t n_cells, int32_t max_iter, void *d_ws, size_t ws_bytes, double *d_theta,
-              void *stream);
+              int32_t *d_status, void *stream);
 
 /* Decisions at continuous points, with gradients (differentiation axis; not
  * in the paper).  For each point theta = (x, y, vx, vy) (d_theta: double

@@ -19,15 +19,35 @@ With E = exp(-j 2 pi (f_r s + f_d m)) and the moments
               - j 2 pi (f_r,ab M_10 + f_d,ab M_01),
   dD/da = 2 Re(conj(c) dc/da),  d2D/da db = 2 Re(conj(dc/db) dc/da + conj(c) d2c/da db).
 
-Iteration (coordinates z = (theta - theta_0) / h, h the grid steps; an axis
-with a single grid point is held fixed):
-  step  = sum_i (e_i . g) / max(|lambda_i|, 1e-12 max|lambda|) e_i over the
-          eigenpairs of the Hessian (the Newton step where the Hessian is
-          negative definite, an ascent step everywhere);
-  stop if every component of the step is below `tol` cells;
+The refined estimate is the converged local maximiser of D over the box
+|theta_a - theta_0,a| <= h_a (one grid step per axis) reached by ascent from
+the starting cell theta_0: the point where the box-projected Newton step
+vanishes (KKT stationarity on the box), found with a generous budget so that
+the answer does not depend on how the search is tuned.  Coordinates
+z = (theta - theta_0) / h; an axis with a single grid point (h = 0) is held.
+One iteration, a projected Newton step for the bound-constrained maximum
+(Bertsekas' projected Newton method, with an epsilon-active set):
+  w     = max_a |clamp(z_a + g_a / L) - z_a|, L the largest |diagonal entry|
+          of the Hessian in z (how far z is from stationary, in cells);
+  eps   = min(EPS_ACTIVE, w);
+  push  = the coordinates within eps of a face of the box whose gradient
+          component points out of it: their step is one cell outwards, so
+          the projection puts them on the face;
+  step  = on the other free coordinates, sum_i (e_i . g) /
+          max(|lambda_i|, 1e-12 max|lambda|) e_i over the eigenpairs of the
+          Hessian in z restricted to them (the Newton step of the reduced
+          problem where its Hessian is negative definite, an ascent direction
+          everywhere);
+  converged when the projected step clamp(z + step) - z is below `tol`
+          cells in every coordinate (the reduced gradient vanishes and every
+          pushed coordinate is on its face: KKT on the box);
   candidate = clamp(z + step, [-1, 1]); while D(candidate) < D(z), halve the
-          step (at most 16 candidates; no ascent -> stop);
-  stop when the accepted move is below `tol` cells or after `max_iter` steps.
+          step (up to `max_halvings` times); move to the candidate;
+  converged also when the accepted move is below `tol` cells (z is then
+          stationary to the precision of D).
+The loop runs at most `max_iter` iterations; refine_one reports whether it
+converged (a search that finds no ascent within `max_halvings` halvings, or
+runs out of iterations, is reported as not converged).
 """
 from __future__ import annotations
 
@@ -36,6 +56,7 @@ import numpy as np
 from . import radar as rd
 
 ORDER = [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (0, 2)]   # (p, q) of the moments M_pq
+EPS_ACTIVE = 1e-2     # cells: the widest band next to a face in which an outward-pushed coordinate is put on it
 
 
 def moments(yq: np.ndarray, fr: float, fd: float) -> dict:
@@ -113,23 +134,34 @@ def grid_steps(grid) -> np.ndarray:
     return np.array([0.0 if grid.n[a] == 1 else (grid.hi[a] - grid.lo[a]) / (grid.n[a] - 1) for a in range(4)])
 
 
-def refine_one(y, radar: rd.Radar, theta0, h, max_iter: int = 20, tol: float = 1e-7):
+def refine_one(y, radar: rd.Radar, theta0, h, max_iter: int = 200, tol: float = 1e-10,
+               max_halvings: int = 60, report: bool = False):
+    """Converged local maximiser of D within one grid step of theta0 (see the module header)."""
     theta0 = np.asarray(theta0, np.float64)
     z = np.zeros(4)
     free = h > 0
     d_cur = decision_value(y, radar, theta0)
-    for _ in range(max_iter):
+    converged = False
+    iters = 0
+    for iters in range(1, max_iter + 1):
         _, g, hth = decision_derivs(y, radar, theta0 + z * h)
         gz = np.where(free, g * h, 0.0)
         hz = hth * np.outer(h, h)
-        lam, vec = np.linalg.eigh(hz)
-        floor = 1e-12 * max(np.max(np.abs(lam)), 1e-300)
-        step = vec @ ((vec.T @ gz) / np.maximum(np.abs(lam), floor))
-        step = np.where(free, step, 0.0)
-        if float(np.max(np.abs(step))) < tol:
+        curv = max(float(np.max(np.abs(np.diag(hz)[free]))) if free.any() else 0.0, 1e-300)
+        w = float(np.max(np.abs(np.clip(z + gz / curv, -1.0, 1.0) - z)))
+        eps = min(EPS_ACTIVE, w)
+        push = free & (((z >= 1.0 - eps) & (gz > 0.0)) | ((z <= -1.0 + eps) & (gz < 0.0)))
+        mov = free & ~push
+        step = np.where(push, np.sign(gz), 0.0)
+        if mov.any():
+            lam, vec = np.linalg.eigh(hz[np.ix_(mov, mov)])
+            floor = 1e-12 * max(np.max(np.abs(lam)), 1e-300)
+            step[mov] = vec @ ((vec.T @ gz[mov]) / np.maximum(np.abs(lam), floor))
+        if float(np.max(np.abs(np.clip(z + step, -1.0, 1.0) - z))) < tol:
+            converged = True
             break
         accepted = False
-        for _ in range(16):
+        for _ in range(max_halvings + 1):
             cand = np.clip(z + step, -1.0, 1.0)
             d_new = decision_value(y, radar, theta0 + cand * h)
             if d_new >= d_cur:
@@ -141,11 +173,18 @@ def refine_one(y, radar: rd.Radar, theta0, h, max_iter: int = 20, tol: float = 1
         move = float(np.max(np.abs(cand - z)))
         z, d_cur = cand, d_new
         if move < tol:
+            converged = True
             break
-    return theta0 + z * h
+    theta = theta0 + z * h
+    return (theta, converged, iters) if report else theta
 
 
-def refine(y, radar: rd.Radar, grid, cells, max_iter: int = 20, tol: float = 1e-7) -> np.ndarray:
-    """Refined (x, y, vx, vy) for each starting cell (linear grid index)."""
+def refine(y, radar: rd.Radar, grid, cells, max_iter: int = 200, tol: float = 1e-10, report: bool = False):
+    """Refined (x, y, vx, vy) for each starting cell (linear grid index); with
+    `report`, also whether each converged and its iteration count."""
     h = grid_steps(grid)
-    return np.stack([refine_one(y, radar, rd.grid_point(grid, int(c)), h, max_iter, tol) for c in cells])
+    res = [refine_one(y, radar, rd.grid_point(grid, int(c)), h, max_iter, tol, report=True) for c in cells]
+    theta = np.stack([r[0] for r in res])
+    if report:
+        return theta, np.array([r[1] for r in res]), np.array([r[2] for r in res])
+    return theta

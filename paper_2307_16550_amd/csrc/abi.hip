@@ -16,6 +16,8 @@
 namespace {
 
 thread_local char g_err[512] = "";
+constexpr int kKnobs = 7;
+thread_local int g_knob[kKnobs] = {};
 
 int fail(int code, const char* fmt, ...) {
     va_list ap;
@@ -344,8 +346,7 @@ static hipError_t bomp_select_launch(const gh::Geom& g, const gh::GridP& gp, con
         if (e == hipSuccess)
             e = gh::launch_gh_sweep(g, gp, d_maps, GH_MAP_C64, interp, nullptr, block, d_support, n_support, st);
     } else {
-        const char* mode = getenv("GH_BOMP_MAPS");
-        const bool fft_only = mode && strcmp(mode, "fft") == 0;
+        const bool fft_only = gh::knob(GH_KNOB_BOMP_MAPS_FFT) != 0;
         float2* rmaps = (float2*)ws;
         if (!fft_only && gh::bomp_resid_maps_ok(g, n_support))
             e = gh::launch_bomp_resid_maps(g, gp, (const float2*)d_maps, atom_vec, n_support, rmaps, st);
@@ -458,13 +459,13 @@ size_t gh_refine_workspace_bytes(const gh_radar* radar, const gh_grid* grid, int
 }
 
 int gh_refine(const gh_radar* radar, const gh_grid* grid, const void* d_y, const int64_t* d_cells, int32_t n_cells,
-              int32_t max_iter, void* d_ws, size_t ws_bytes, double* d_theta, void* stream) {
+              int32_t max_iter, void* d_ws, size_t ws_bytes, double* d_theta, int32_t* d_status, void* stream) {
     gh::Geom g;
     gh::GridP gp;
     int rc = make_geom(radar, g);
     if (rc || (rc = make_grid(grid, gp))) return rc;
     if (!d_y || !d_cells || !d_theta) return fail(GH_EINVAL, "NULL device pointer");
-    if ((rc = check_aligned({d_y, d_cells, d_ws, d_theta}))) return rc;
+    if ((rc = check_aligned({d_y, d_cells, d_ws, d_theta, d_status}))) return rc;
     if (n_cells < 0 || n_cells > 65535) return fail(GH_EINVAL, "n_cells must be in [0, 65535]");
     if (max_iter < 1 || max_iter > 100) return fail(GH_EINVAL, "max_iter must be in [1, 100]");
     if (n_cells == 0) return ok();
@@ -473,7 +474,7 @@ int gh_refine(const gh_radar* radar, const gh_grid* grid, const void* d_y, const
     if (ws_bytes < need) return fail(GH_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if ((rc = check_device())) return rc;
     hipError_t e = gh::launch_refine(g, gp, (const float2*)d_y, d_cells, n_cells, max_iter, d_ws, d_theta,
-                                     (hipStream_t)stream);
+                                     d_status, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gh_refine launch");
     return ok();
 }
@@ -771,3 +772,27 @@ int gh_batch_frame_maps(const gh_batch* batch, int32_t frame, void** d_maps) {
 void gh_batch_destroy(gh_batch* batch) { delete batch; }
 
 }  // extern "C"
+
+namespace gh {
+int knob(int which) { return (which > 0 && which < kKnobs) ? g_knob[which] : 0; }
+}  // namespace gh
+
+extern "C" int gh_test_set_knob(int32_t knob, int32_t value) {
+    int lo = 0, hi = 1;
+    switch (knob) {
+        case GH_KNOB_SWEEP_GENERIC: case GH_KNOB_BOMP_MAPS_FFT: case GH_KNOB_REFINE_SINGLE: break;
+        case GH_KNOB_SWEEP_LDS_KIB: hi = 160; break;
+        case GH_KNOB_REFINE_ROWS: hi = 4096; break;
+        case GH_KNOB_REFINE_SPIN_LIMIT: hi = 1 << 30; break;
+        default: return fail(GH_EINVAL, "unknown switch %d", knob);
+    }
+    if (value < lo || value > hi) return fail(GH_EINVAL, "switch %d: value %d outside [%d, %d]", knob, value, lo, hi);
+    if (knob == GH_KNOB_SWEEP_LDS_KIB && value != 0 && value < 8)
+        return fail(GH_EINVAL, "switch %d: LDS budget below 8 KiB", knob);
+    if (knob == GH_KNOB_REFINE_ROWS && value != 0 && !pow2(value))
+        return fail(GH_EINVAL, "switch %d: rows per workgroup must be a power of two", knob);
+    const int prev = g_knob[knob];
+    g_knob[knob] = value;
+    ok();
+    return prev;
+}

@@ -7,8 +7,12 @@
 #include <stdint.h>
 
 #include "gridhop.h"
+#include "gridhop_test.h"
 
 namespace gh {
+
+// Per-thread override of a test switch (gridhop_test.h); 0 = default.
+int knob(int which);
 
 constexpr int kMaxRx = GH_MAX_RX;
 constexpr int kMaxSupport = GH_MAX_SUPPORT;
@@ -345,8 +349,10 @@ hipError_t launch_bomp_resid_maps(const Geom& g, const GridP& gp, const float2* 
                                   int nsel, float2* out, hipStream_t st);
 
 size_t refine_ws_bytes(const Geom& g, int ncells);
+// status (nullable): int32, set to the number of cells whose estimate is NaN
+// (a cluster barrier wait expired).
 hipError_t launch_refine(const Geom& g, const GridP& gp, const float2* y, const int64_t* cells, int ncells,
-                         int max_iter, void* ws, double* theta, hipStream_t st);
+                         int max_iter, void* ws, double* theta, int* status, hipStream_t st);
 
 size_t direct_points_ws_bytes(const Geom& g, int npts);
 hipError_t launch_direct_points(const Geom& g, const float2* y, const double* theta, int npts, void* ws,

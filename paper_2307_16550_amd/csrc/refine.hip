@@ -14,12 +14,14 @@
 // (or as many as the scratch holds) share one pass: their (receiver, chirp)
 // rows are spread over the workgroup and reduced by segment.
 // Coordinates are scaled by the grid steps (an axis with one grid point is
-// held); the step uses the Hessian's eigenpairs with eigenvalues replaced by
-// -|lambda| (cyclic Jacobi, FP64); the ascent stops when every step component
-// is below 1e-7 steps; otherwise the step is halved until the decision does
-// not decrease (at most 16 candidates) and clamped to +-1 grid step.
-#include <stdlib.h>
-#include <string.h>
+// held) and kept in the box of +-1 grid step around the cell.  Each iteration
+// takes a projected Newton step (Bertsekas, with an epsilon-active set: a
+// coordinate next to a face whose gradient points outwards is put on the
+// face, the others take the Newton step of the problem restricted to them,
+// eigenvalues replaced by -|lambda|); the ascent stops when the projected step
+// is below 1e-7 steps in every coordinate (KKT on the box); otherwise the step
+// is halved until the decision does not decrease (at most 16 candidates).
+// The answer is the converged local maximum of D on the box.
 
 #include "gh_internal.h"
 #include "lane_sum.h"
@@ -29,6 +31,7 @@ namespace {
 
 constexpr int kThreads = 1024;
 constexpr double kTol = 1e-7;
+constexpr double kEpsActive = 1e-2;   // cells: widest band next to a face where an outward push puts a coordinate on it
 
 
 // f_r, f_d and their first and second derivatives, kept to the structurally
@@ -321,13 +324,21 @@ __device__ __forceinline__ void newton_terms(const Geom& g, int q, const double 
     }
 }
 
-// Newton step in grid-step coordinates from the summed gradient and Hessian:
-// step = sum_i (e_i . g) / max(|lambda_i|, 1e-12 max|lambda|) e_i over the
-// eigenpairs of the scaled Hessian.  Where the Hessian is negative definite
-// with a moderate condition number this is (-H)^-1 g, solved by Cholesky;
-// otherwise by the cyclic Jacobi eigen-decomposition.
-__device__ __forceinline__ void newton_solve(const double t[14], const double h[4], double step[4]) {
+// Projected Newton step in grid-step coordinates z (the box |z_a| <= 1) from
+// the summed gradient and Hessian, with an epsilon-active set:
+//   w = max_a |clamp(z_a + g_a / L) - z_a| (L: the largest |Hessian diagonal|),
+//   eps = min(kEpsActive, w); a free coordinate within eps of a face whose
+//   gradient points out of the box is pushed one cell outwards (the clamp of
+//   the candidates puts it on the face); on the other free coordinates
+//   step = sum_i (e_i . g) / max(|lambda_i|, 1e-12 max|lambda|) e_i over the
+//   eigenpairs of the Hessian restricted to them.
+// Where that restricted Hessian is negative definite with a moderate condition
+// number the step is (-H)^-1 g, solved by Cholesky; otherwise by the cyclic
+// Jacobi eigen-decomposition.  A held axis (one grid point) has step 0.
+__device__ __forceinline__ void newton_solve(const double t[14], const double h[4], const double z[4],
+                                             double step[4]) {
     double gz[4], hz[4][4];
+    bool mov[4], push[4];
     int k = 4;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -338,16 +349,26 @@ __device__ __forceinline__ void newton_solve(const double t[14], const double h[
             hz[b][a] = hz[a][b];
         }
     }
-    // Cholesky of -H on the free axes (a held axis gets a unit row and no gradient)
+    double curv = 1e-300;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+        if (h[a] > 0.0) curv = fmax(curv, fabs(hz[a][a]));
+    double w = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) w = fmax(w, fabs(fmin(1.0, fmax(-1.0, z[a] + gz[a] / curv)) - z[a]));
+    const double eps = fmin(kEpsActive, w);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        push[a] = h[a] > 0.0 && ((z[a] >= 1.0 - eps && gz[a] > 0.0) || (z[a] <= -1.0 + eps && gz[a] < 0.0));
+        mov[a] = h[a] > 0.0 && !push[a];
+    }
+    // Cholesky of -H on the moving axes (any other axis gets a unit row and no gradient)
     double l[4][4], dmax = 0.0;
     bool spd = true;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const bool fa = h[a] > 0.0, fb = h[b] > 0.0;
-            l[a][b] = (fa && fb) ? -hz[a][b] : (a == b ? 1.0 : 0.0);
-        }
+        for (int b = 0; b < 4; ++b) l[a][b] = (mov[a] && mov[b]) ? -hz[a][b] : (a == b ? 1.0 : 0.0);
 #pragma unroll
     for (int a = 0; a < 4; ++a) dmax = fmax(dmax, fabs(l[a][a]));
 #pragma unroll
@@ -366,51 +387,66 @@ __device__ __forceinline__ void newton_solve(const double t[14], const double h[
             l[i][j] = v / ljj;
         }
     }
+    double gm[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) gm[a] = mov[a] ? gz[a] : 0.0;
     if (spd) {
-        double w[4];
+        double wv[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            double v = gz[i];
+            double v = gm[i];
 #pragma unroll
-            for (int k2 = 0; k2 < i; ++k2) v -= l[i][k2] * w[k2];
-            w[i] = v / l[i][i];
+            for (int k2 = 0; k2 < i; ++k2) v -= l[i][k2] * wv[k2];
+            wv[i] = v / l[i][i];
         }
 #pragma unroll
         for (int i = 3; i >= 0; --i) {
-            double v = w[i];
+            double v = wv[i];
 #pragma unroll
             for (int k2 = i + 1; k2 < 4; ++k2) v -= l[k2][i] * step[k2];
             step[i] = v / l[i][i];
         }
+    } else {
+        double hm[4][4], vec[4][4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) step[a] = (h[a] > 0.0) ? step[a] : 0.0;
-        return;
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) hm[a][b] = (mov[a] && mov[b]) ? hz[a][b] : 0.0;
+        jacobi4(hm, vec);
+        double lmax = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) lmax = fmax(lmax, fabs(hm[a][a]));
+        const double floor_l = 1e-12 * fmax(lmax, 1e-300);
+        double coef[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double p = 0.0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) p += vec[a][i] * gm[a];
+            coef[i] = p / fmax(fabs(hm[i][i]), floor_l);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s += vec[a][i] * coef[i];
+            step[a] = s;
+        }
     }
-    double vec[4][4];
-    jacobi4(hz, vec);
-    double lmax = 0.0;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) lmax = fmax(lmax, fabs(hz[a][a]));
-    const double floor_l = 1e-12 * fmax(lmax, 1e-300);
-    double coef[4];
+    for (int a = 0; a < 4; ++a) step[a] = push[a] ? (gz[a] > 0.0 ? 1.0 : -1.0) : (mov[a] ? step[a] : 0.0);
+}
+
+// Largest component of the projected step clamp(z + step) - z.
+__device__ __forceinline__ double projected_step(const double z[4], const double step[4]) {
+    double m = 0.0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        double p = 0.0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) p += vec[a][i] * gz[a];
-        coef[i] = p / fmax(fabs(hz[i][i]), floor_l);
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) s += vec[a][i] * coef[i];
-        step[a] = (h[a] > 0.0) ? s : 0.0;
-    }
+    for (int a = 0; a < 4; ++a) m = fmax(m, fabs(fmin(1.0, fmax(-1.0, z[a] + step[a])) - z[a]));
+    return m;
 }
 
 // Newton step from the moments of every receiver (one thread).
-__device__ __forceinline__ void newton_step(const Geom& g, const double th[4], const double h[4],
+__device__ __forceinline__ void newton_step(const Geom& g, const double th[4], const double h[4], const double z[4],
                                             const double (*mom)[12], double step[4]) {
     double t[14];
 #pragma unroll
@@ -421,7 +457,7 @@ __device__ __forceinline__ void newton_step(const Geom& g, const double th[4], c
 #pragma unroll
         for (int i = 0; i < 14; ++i) t[i] += c[i];
     }
-    newton_solve(t, h, step);
+    newton_solve(t, h, z, step);
 }
 
 __device__ __forceinline__ void start_point(const GridP& gp, int64_t idx, double th0[4]) {
@@ -461,15 +497,12 @@ __global__ __launch_bounds__(kThreads) void refine_single_kernel(Geom g, GridP g
             for (int q0 = 0; q0 < g.k; q0 += gs)
                 moments_group(g, y, th, q0, (g.k - q0 < gs) ? g.k - q0 : gs, true, sc, mom);
         }
-        if (tid == 0) newton_step(g, th, h, mom, sh_step);
+        if (tid == 0) newton_step(g, th, h, z, mom, sh_step);
         __syncthreads();
-        double step[4], smax = 0.0;
+        double step[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            step[a] = sh_step[a];
-            smax = fmax(smax, fabs(step[a]));
-        }
-        if (smax < kTol) break;
+        for (int a = 0; a < 4; ++a) step[a] = sh_step[a];
+        if (projected_step(z, step) < kTol) break;
         bool accepted = false;
         double cand[4], d_new = 0.0;
         for (int tries = 0; tries < 16; ++tries) {
@@ -547,6 +580,7 @@ struct Cluster {
     int rows_per_wg;   // R, a power of two (a divisor or a multiple of Mc)
     int wgs;           // W = ceil(K Mc / R)
     int slots;         // partial-buffer slots (workgroups of one launch)
+    unsigned spin_limit;   // polls before a barrier wait expires
 };
 
 struct ClusterShared {
@@ -567,7 +601,7 @@ struct ClusterShared {
 // Cluster barrier: arrival count `target` on this cell's counter.  Bounded: a
 // wait that exceeds the spin limit, or sees the launch's abort flag, raises the
 // flag and returns false (every waiting workgroup then leaves).
-__device__ bool cell_barrier(unsigned* ctr, unsigned target, unsigned* abort_flag, int* ok_sh) {
+__device__ bool cell_barrier(unsigned* ctr, unsigned target, unsigned* abort_flag, unsigned spin_limit, int* ok_sh) {
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
@@ -576,7 +610,7 @@ __device__ bool cell_barrier(unsigned* ctr, unsigned target, unsigned* abort_fla
         unsigned spins = 0;
         while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-                ++spins > kSpinLimit) {
+                ++spins > spin_limit) {
                 atomicExch(abort_flag, 1u);
                 ok = 0;
                 break;
@@ -787,7 +821,7 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
             part[((((size_t)par * cl.slots + cx.slot0 + cx.part) * kCand + cc) * kMaxRx + i) * 12 + k] = t;
         }
     }
-    const bool ok = cell_barrier(ctr + cx.cell, (pass + 1u) * (unsigned)cl.wgs, abort_flag, &sh.ok);
+    const bool ok = cell_barrier(ctr + cx.cell, (pass + 1u) * (unsigned)cl.wgs, abort_flag, cl.spin_limit, &sh.ok);
     if (ok) {
         const int par = (int)(pass & 1u);
         const int per_q = R < mc ? mc / R : 1;         // workgroups holding one receiver
@@ -819,7 +853,7 @@ __global__ __launch_bounds__(kCT) void refine_cluster_kernel(Geom g, GridP gp, c
                                                             const int64_t* __restrict__ cells, int cell0,
                                                             int max_iter, Cluster cl,
                                                             double* __restrict__ theta_out, unsigned* ctr,
-                                                            unsigned* abort_flag, double* part) {
+                                                            unsigned* abort_flag, double* part, int* status) {
     extern __shared__ float4 er4[];                 // range phase factors of one pass
     __shared__ ClusterShared sh;
     float2* er = reinterpret_cast<float2*>(er4);
@@ -861,16 +895,13 @@ __global__ __launch_bounds__(kCT) void refine_cluster_kernel(Geom g, GridP gp, c
             double t[14];
 #pragma unroll
             for (int i = 0; i < 14; ++i) t[i] = sh.tsum[i];
-            newton_solve(t, h, sh.step);
+            newton_solve(t, h, z, sh.step);
         }
         __syncthreads();
-        double step[4], smax = 0.0;
+        double step[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            step[a] = sh.step[a];
-            smax = fmax(smax, fabs(step[a]));
-        }
-        if (smax < kTol) break;
+        for (int a = 0; a < 4; ++a) step[a] = sh.step[a];
+        if (projected_step(z, step) < kTol) break;
         int acc_c = -1;
         for (int tries = 0; tries < 16 && acc_c < 0;) {
             const int npts = 16 - tries < kCand ? 16 - tries : kCand;
@@ -908,14 +939,18 @@ __global__ __launch_bounds__(kCT) void refine_cluster_kernel(Geom g, GridP gp, c
         __syncthreads();
         if (move < kTol) break;
     }
-    if (cx.part == 0 && tid == 0)
+    if (cx.part == 0 && tid == 0) {
 #pragma unroll
         for (int a = 0; a < 4; ++a) theta_out[(size_t)cx.cell * 4 + a] = ok ? th0[a] + z[a] * h[a] : NAN;
+        if (!ok && status) atomicAdd(status, 1);
+    }
 }
 
-__global__ void refine_clear_kernel(unsigned* p, int n) {
+// Zeroes the barrier counters and the abort flag (n words) and the status word.
+__global__ void refine_clear_kernel(unsigned* p, int n, int* status) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
+    if (i == 0 && status) *status = 0;
 }
 
 int pow2_at_least(int v) {
@@ -931,6 +966,7 @@ Cluster cluster_plan(const Geom& g, int rows_per_wg, int ncells) {
     cl.wgs = (rows + rows_per_wg - 1) / rows_per_wg;
     const long slots = (long)ncells * cl.wgs;
     cl.slots = (int)(slots < kSlotsMax ? slots : kSlotsMax);
+    cl.spin_limit = kSpinLimit;
     return cl;
 }
 
@@ -944,14 +980,11 @@ int rows_max(const Geom& g) {
     return r < kRowsMinC ? kRowsMinC : r;
 }
 
-// Preferred rows per workgroup: about kWgsTarget workgroups per cell.
-// GH_REFINE_ROWS overrides it (tuning).
+// Preferred rows per workgroup: about kWgsTarget workgroups per cell (the
+// GH_KNOB_REFINE_ROWS test switch overrides it).
 int rows_pref(const Geom& g) {
     int r = pow2_at_least((g.k * g.mc + kWgsTarget - 1) / kWgsTarget);
-    if (const char* e = getenv("GH_REFINE_ROWS")) {
-        const int v = atoi(e);
-        if (v > 0 && (v & (v - 1)) == 0) r = v;
-    }
+    if (const int v = knob(GH_KNOB_REFINE_ROWS)) r = v;
     const int hi = rows_max(g);
     if (r > hi) r = hi;
     return r < kRowsMinC ? kRowsMinC : r;
@@ -970,10 +1003,9 @@ size_t refine_ws_bytes(const Geom& g, int ncells) {
 }
 
 hipError_t launch_refine(const Geom& g, const GridP& gp, const float2* y, const int64_t* cells, int ncells,
-                         int max_iter, void* ws, double* theta, hipStream_t st) {
-    // GH_REFINE_KERNEL = single selects the one-workgroup-per-cell kernel (diagnostics and tests)
-    const char* sel = getenv("GH_REFINE_KERNEL");
-    const bool single_only = sel && strcmp(sel, "single") == 0;
+                         int max_iter, void* ws, double* theta, int* status, hipStream_t st) {
+    // the one-workgroup-per-cell kernel when the test switch asks for it
+    const bool single_only = knob(GH_KNOB_REFINE_SINGLE) != 0;
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -1002,14 +1034,21 @@ hipError_t launch_refine(const Geom& g, const GridP& gp, const float2* y, const 
         found = true;
         if ((long)ncells * c.wgs <= cap) break;     // one launch holds every cell
     }
+    unsigned* ctr = static_cast<unsigned*>(ws);
     if (single_only || !found) {
+        // no barriers: the status is zero
+        if (status) {
+            hipLaunchKernelGGL(refine_clear_kernel, dim3(1), dim3(64), 0, st, ctr, 0, status);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
         hipLaunchKernelGGL(refine_single_kernel, dim3(ncells), dim3(kThreads), 0, st, g, gp, y, cells, max_iter, theta);
         return hipGetLastError();
     }
-    unsigned* ctr = static_cast<unsigned*>(ws);
+    const int spin = knob(GH_KNOB_REFINE_SPIN_LIMIT);
+    cl.spin_limit = spin > 0 ? (unsigned)spin : kSpinLimit;
     unsigned* abort_flag = ctr + ncells;
     double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + counters_bytes(ncells));
-    hipLaunchKernelGGL(refine_clear_kernel, dim3((ncells + 256) / 256), dim3(256), 0, st, ctr, ncells + 1);
+    hipLaunchKernelGGL(refine_clear_kernel, dim3((ncells + 256) / 256), dim3(256), 0, st, ctr, ncells + 1, status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int batch = (int)(capacity / cl.wgs);
     for (int c0 = 0; c0 < ncells; c0 += batch) {
@@ -1021,7 +1060,8 @@ hipError_t launch_refine(const Geom& g, const GridP& gp, const float2* y, const 
         int c0a = c0, mi = max_iter;
         Cluster cla = cl;
         double* ta = theta;
-        void* args[] = {&ga, &gpa, &ya, &ca, &c0a, &mi, &cla, &ta, &ctr, &abort_flag, &part};
+        int* sa = status;
+        void* args[] = {&ga, &gpa, &ya, &ca, &c0a, &mi, &cla, &ta, &ctr, &abort_flag, &part, &sa};
         e = hipLaunchKernel(reinterpret_cast<const void*>(refine_cluster_kernel), dim3(nb * cl.wgs), dim3(kCT), args,
                             lds, st);
         if (e != hipSuccess) return e;

@@ -275,15 +275,11 @@ void launch_generic(const Geom& g, const GridP& gp, const char* maps, int interp
 
 hipError_t launch_gh_sweep(const Geom& g, const GridP& gp, const void* maps, int map_dtype, int interp, float* dec,
                            gh_peak* block, const int64_t* excl, int nexcl, hipStream_t st) {
-    // GH_SWEEP_KERNEL = columns | generic restricts the variant (diagnostics and tuning)
-    static const int only = [] {
-        const char* s = getenv("GH_SWEEP_KERNEL");
-        if (!s) return 0;
-        return strcmp(s, "columns") == 0 ? 2 : strcmp(s, "generic") == 0 ? 3 : 0;
-    }();
+    // the generic kernel for every shape when the test switch asks for it
+    const bool generic_only = knob(GH_KNOB_SWEEP_GENERIC) != 0;
     int lpb = 0, log2nvy = 0;
     size_t lds_cols = 0;
-    if ((only == 0 || only == 2) && sweep_columns_plan(g, gp, interp, lpb, log2nvy, lds_cols))
+    if (!generic_only && sweep_columns_plan(g, gp, interp, lpb, log2nvy, lds_cols))
         return launch_gh_sweep_columns(g, gp, lpb, log2nvy, lds_cols, maps, map_dtype, interp, dec, block, excl, nexcl,
                                        st);
     const char* m = static_cast<const char*>(maps);

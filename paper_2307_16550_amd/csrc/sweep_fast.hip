@@ -31,8 +31,6 @@
 // The volume and the block maxima are written once, after the last receiver.
 // Maps stored as 16-bit float pairs (Z / (Ms Mc)) are widened to FP32 in the
 // table build, with the storage scale folded into the range weights.
-#include <stdlib.h>
-
 #include "sweep_table.h"
 
 namespace gh {
@@ -211,11 +209,8 @@ bool sweep_columns_plan(const Geom& g, const GridP& gp, int interp, int& lpb, in
     if (chunk > 32) return false;
     if (g.nd < 16) return false;
     const size_t entry = interp ? 32 : 16;
-    static const long budget_env = [] {
-        const char* s = getenv("GH_SWEEP_LDS_KB");   // tuning override of the LDS budget
-        return s ? atol(s) : 0L;
-    }();
-    const size_t lds_budget = (budget_env > 0 ? (size_t)budget_env : 40) * 1024;
+    const int budget_kib = knob(GH_KNOB_SWEEP_LDS_KIB);   // test switch; default 40 KiB
+    const size_t lds_budget = (budget_kib > 0 ? (size_t)budget_kib : 40) * 1024;
     const int cap = kThreads / 64;                   // one location per wave
     const int fit = (int)(lds_budget / ((size_t)g.nd * entry + (size_t)g.k * sizeof(FastGeo)));
     lpb = cap < fit ? cap : fit;

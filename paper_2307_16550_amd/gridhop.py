@@ -30,7 +30,7 @@ EXPORTS = ("gh_abi_version", "gh_last_error", "gh_rd_maps", "gh_decision", "gh_a
            "gh_refine", "gh_direct_points_workspace_bytes", "gh_direct_points", "gh_gh_points",
            "gh_range_spectra", "gh_factored_workspace_bytes", "gh_factored_decision",
            "gh_batch_workspace_bytes", "gh_batch_create", "gh_batch_tune", "gh_batch_get_info", "gh_batch_run",
-           "gh_batch_frame_maps", "gh_batch_destroy")
+           "gh_batch_frame_maps", "gh_batch_destroy", "gh_test_set_knob")
 
 
 class GhRadar(ctypes.Structure):
@@ -94,7 +94,9 @@ def load():
     lib.gh_bomp_fit.argtypes = [rp, gp_, vp, vp, vp, i32, i32, vp, vp, sz, vp]
     lib.gh_refine_workspace_bytes.argtypes = [rp, gp_, i32]
     lib.gh_refine_workspace_bytes.restype = sz
-    lib.gh_refine.argtypes = [rp, gp_, vp, vp, i32, i32, vp, sz, vp, vp]
+    lib.gh_refine.argtypes = [rp, gp_, vp, vp, i32, i32, vp, sz, vp, vp, vp]
+    lib.gh_test_set_knob.argtypes = [i32, i32]
+    lib.gh_test_set_knob.restype = ctypes.c_int
     lib.gh_direct_points_workspace_bytes.argtypes = [rp, i32]
     lib.gh_direct_points_workspace_bytes.restype = sz
     lib.gh_direct_points.argtypes = [rp, vp, vp, i32, vp, vp, vp, vp, sz, vp]
@@ -348,7 +350,10 @@ def refine_workspace_bytes(radar: Radar, grid: GhGrid, n_cells: int) -> int:
     return n
 
 
-def refine(radar: Radar, grid: GhGrid, y, cells: torch.Tensor, max_iter=20, theta=None, ws=None, stream=None):
+def refine(radar: Radar, grid: GhGrid, y, cells: torch.Tensor, max_iter=20, theta=None, ws=None, status=None,
+           stream=None):
+    """Refined (x, y, vx, vy) [n, 4] from each starting cell; `status` (int32 [1], optional)
+    receives the number of cells left NaN by an expired cluster barrier."""
     lib = load()
     _c64(y)
     if cells.dtype != torch.int64 or not cells.is_cuda:
@@ -358,9 +363,34 @@ def refine(radar: Radar, grid: GhGrid, y, cells: torch.Tensor, max_iter=20, thet
     if ws is None and cells.numel() > 0:
         ws = torch.empty(refine_workspace_bytes(radar, grid, cells.numel()), dtype=torch.uint8, device=y.device)
     nws = 0 if ws is None else ws.numel()
+    if status is not None and (status.dtype != torch.int32 or not status.is_cuda or status.numel() < 1):
+        raise ValueError("status must be an int32 CUDA tensor with at least one element")
     _check(lib.gh_refine(ctypes.byref(radar.c_struct), ctypes.byref(grid), _ptr(y), _ptr(cells), cells.numel(),
-                         int(max_iter), _ptr(ws), nws, _ptr(theta), _stream(stream)))
+                         int(max_iter), _ptr(ws), nws, _ptr(theta), _ptr(status), _stream(stream)))
     return theta
+
+
+GH_KNOB_SWEEP_GENERIC, GH_KNOB_SWEEP_LDS_KIB, GH_KNOB_BOMP_MAPS_FFT = 1, 2, 3
+GH_KNOB_REFINE_SINGLE, GH_KNOB_REFINE_ROWS, GH_KNOB_REFINE_SPIN_LIMIT = 4, 5, 6
+
+
+class knob:
+    """Context manager of a test switch (include/gridhop_test.h) for the calling thread:
+    `with knob(GH_KNOB_BOMP_MAPS_FFT, 1): ...` restores the previous value on exit."""
+
+    def __init__(self, which: int, value: int):
+        self.which, self.value, self.prev = int(which), int(value), None
+
+    def __enter__(self):
+        rc = load().gh_test_set_knob(self.which, self.value)
+        if rc < 0:
+            raise GridHopError(rc, last_error())
+        self.prev = rc
+        return self
+
+    def __exit__(self, *exc):
+        load().gh_test_set_knob(self.which, self.prev)
+        return False
 
 
 def _points_outputs(theta, k, want_grad, want_grad_rx):

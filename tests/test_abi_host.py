@@ -14,9 +14,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    text = open(os.path.join(ROOT, "include", "gridhop.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(gh_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in ("gridhop.h", "gridhop_test.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(gh_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -34,7 +37,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.gh_abi_version() == 1
+    assert lib.gh_abi_version() == 2
 
 
 def radar(**kw):
@@ -113,10 +116,11 @@ def test_bomp_and_refine_argument_checks(lib):
     assert rws >= 2 * 3 * 3 * 12 * 8
     assert lib.gh_refine_workspace_bytes(ctypes.byref(r.c_struct), ctypes.byref(GRID), 0) == 0
     rargs = [ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, FAKE]
-    assert lib.gh_refine(*rargs, 1, 0, FAKE, rws, FAKE, None) == gh.GH_EINVAL           # max_iter 0
-    assert lib.gh_refine(*rargs, 3, 20, FAKE, rws - 1, FAKE, None) == gh.GH_EWORKSPACE
-    assert lib.gh_refine(*rargs, 3, 20, None, rws, FAKE, None) == gh.GH_EINVAL
-    assert lib.gh_refine(*rargs, 0, 20, None, 0, FAKE, None) == gh.GH_OK
+    assert lib.gh_refine(*rargs, 1, 0, FAKE, rws, FAKE, None, None) == gh.GH_EINVAL           # max_iter 0
+    assert lib.gh_refine(*rargs, 3, 20, FAKE, rws - 1, FAKE, None, None) == gh.GH_EWORKSPACE
+    assert lib.gh_refine(*rargs, 3, 20, None, rws, FAKE, None, None) == gh.GH_EINVAL
+    assert lib.gh_refine(*rargs, 3, 20, FAKE, rws, FAKE, ctypes.c_void_p(0x1004), None) == gh.GH_EINVAL  # status misaligned
+    assert lib.gh_refine(*rargs, 0, 20, None, 0, FAKE, None, None) == gh.GH_OK
 
 
 def test_bomp_select_and_fit_argument_checks(lib):
@@ -137,7 +141,8 @@ def test_error_message_cleared_after_success(lib):
     r = radar()
     lib.gh_rd_maps(None, FAKE, FAKE, 0, None)
     assert gh.last_error()
-    assert lib.gh_refine(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, FAKE, 0, 20, None, 0, FAKE, None) == gh.GH_OK
+    assert lib.gh_refine(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, FAKE, 0, 20, None, 0, FAKE, None,
+                         None) == gh.GH_OK
     assert gh.last_error() == ""
 
 
@@ -152,7 +157,7 @@ def test_misaligned_pointers_rejected(lib):
     assert lib.gh_direct_decision(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, 1, odd, need, None, FAKE,
                                   None, None) == gh.GH_EINVAL
     assert lib.gh_refine(ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, odd, 1, 20, FAKE, 1 << 20, FAKE,
-                         None) == gh.GH_EINVAL
+                         None, None) == gh.GH_EINVAL
 
 
 def test_map_storage_checks(lib):
@@ -292,3 +297,31 @@ def test_missing_library_fails_loudly(monkeypatch):
         gh.load()
     with pytest.raises(ImportError):
         gh.last_error()
+
+
+def test_test_switches(lib):
+    """gh_test_set_knob: per-thread overrides with range checks, the previous value returned."""
+    assert lib.gh_test_set_knob(99, 1) == gh.GH_EINVAL
+    assert lib.gh_test_set_knob(gh.GH_KNOB_BOMP_MAPS_FFT, 2) == gh.GH_EINVAL
+    assert lib.gh_test_set_knob(gh.GH_KNOB_REFINE_ROWS, 24) == gh.GH_EINVAL       # not a power of two
+    assert lib.gh_test_set_knob(gh.GH_KNOB_SWEEP_LDS_KIB, 4) == gh.GH_EINVAL      # below 8 KiB
+    assert lib.gh_test_set_knob(gh.GH_KNOB_REFINE_ROWS, 16) == 0
+    assert lib.gh_test_set_knob(gh.GH_KNOB_REFINE_ROWS, 0) == 16
+    with gh.knob(gh.GH_KNOB_REFINE_SPIN_LIMIT, 5):
+        assert lib.gh_test_set_knob(gh.GH_KNOB_REFINE_SPIN_LIMIT, 5) == 5
+    assert lib.gh_test_set_knob(gh.GH_KNOB_REFINE_SPIN_LIMIT, 0) == 0
+    import threading
+    seen = []
+    with gh.knob(gh.GH_KNOB_SWEEP_GENERIC, 1):
+        th = threading.Thread(target=lambda: seen.append(lib.gh_test_set_knob(gh.GH_KNOB_SWEEP_GENERIC, 0)))
+        th.start()
+        th.join()
+    assert seen == [0]      # another thread's switches are its own
+
+
+def test_library_reads_no_environment():
+    """No product source reads the environment: behaviour depends on arguments only."""
+    for root, _, files in os.walk(os.path.join(ROOT, "paper_2307_16550_amd", "csrc")):
+        for f in files:
+            text = open(os.path.join(root, f)).read()
+            assert "getenv" not in text, f
