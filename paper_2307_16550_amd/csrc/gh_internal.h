@@ -78,6 +78,22 @@ __host__ __device__ __forceinline__ uint32_t cycles_to_fixed(double cyc) {
     return (uint32_t)(r & 0xffffffffull);
 }
 
+// Round a phase in cycles to 64-bit fixed point (53 significant bits), modulo
+// 1 cycle: the phase of sample n is then (fixed * n) mod 2^64, exact.
+__host__ __device__ __forceinline__ uint64_t cycles_to_fixed64(double cyc) {
+    const double f = cyc - floor(cyc);                       // [0, 1]
+    const unsigned long long r = (unsigned long long)(f * 9007199254740992.0 + 0.5);   // 2^53
+    return (uint64_t)(r & ((1ull << 53) - 1)) << 11;
+}
+
+// exp(-j 2 pi ph / 2^64) in FP64.
+__device__ __forceinline__ double2 expm_fixed64(uint64_t ph) {
+    double s, c;
+    // sin/cos of pi * x with x = 2 * ph * 2^-64 in [0, 2), from the top 53 bits
+    sincospi((double)(ph >> 11) * 2.220446049250313e-16, &s, &c);
+    return make_double2(c, -s);
+}
+
 // Signed increment in cycles to a 32-bit two's complement fixed-point step.
 __host__ __device__ __forceinline__ uint32_t cycles_to_fixed_step(double cyc) {
     return cycles_to_fixed(cyc);  // modular arithmetic: the step is also taken mod 1 cycle

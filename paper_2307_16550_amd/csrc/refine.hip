@@ -10,7 +10,11 @@
 // (eqs. (1)-(2)).  The atom is separable, so the moments are two reductions:
 // per chirp A_p[m] = sum_s s^p e_r[s] Y[m][s] (p <= 2), then
 // M_pq = sum_m m^q e_d[m] A_p[m]; only Ms + Mc phase factors are evaluated per
-// receiver (32-bit fixed-point phases, FP64 accumulation).  All receivers
+// receiver.  Everything is FP64: phases in 64-bit fixed point (cycles, exact
+// modulo 1), phase factors by FP64 sincos, products and sums in FP64 (on the
+// matrix cores, FP64 tiles).  Near a flat maximum the ascent's decisions
+// compare values of D that differ in their 8th digit or beyond, so FP32 sums
+// would stop it short of the maximum.  All receivers
 // (or as many as the scratch holds) share one pass: their (receiver, chirp)
 // rows are spread over the workgroup and reduced by segment.
 // Coordinates are scaled by the grid steps (an axis with one grid point is
@@ -150,14 +154,14 @@ __device__ __forceinline__ void jacobi4(double a[4][4], double v[4][4]) {
 }
 
 constexpr int kTab = 3072;       // phase factors of one receiver group (e_r then e_d per receiver)
-constexpr int kRowsMax = 512;    // (receiver, chirp) rows per group
-constexpr int kSegMax = 64;      // reduction segments per group
+constexpr int kRowsMax = 1024;   // (receiver, chirp) rows per group: one per thread
+constexpr int kSegMax = kRowsMax / 16;   // reduction segments per group (at least 16 rows each)
 
 struct Scratch {
-    float2 tab[kTab];
+    double2 tab[kTab];
     double2 a[3][kRowsMax];      // A_p of each row
     double seg[kSegMax][12];     // per-segment partial moments
-    uint32_t frx[kMaxRx], fdx[kMaxRx];
+    uint64_t frx[kMaxRx], fdx[kMaxRx];
 };
 
 // Receivers per pass: the group's phase tables and rows must fit the scratch.
@@ -178,13 +182,13 @@ __device__ __forceinline__ void moments_group(const Geom& g, const float2* __res
     if (tid < G) {
         FreqC f;
         freq_compact(g, q0 + tid, th, f);
-        sc.frx[tid] = cycles_to_fixed(f.fr);
-        sc.fdx[tid] = cycles_to_fixed(f.fd);
+        sc.frx[tid] = cycles_to_fixed64(f.fr);
+        sc.fdx[tid] = cycles_to_fixed64(f.fd);
     }
     __syncthreads();
     for (int e = tid; e < G * span; e += kThreads) {
         const int qq = e / span, r = e - qq * span;
-        sc.tab[e] = (r < ms) ? expm_fixed(sc.frx[qq] * (uint32_t)r) : expm_fixed(sc.fdx[qq] * (uint32_t)(r - ms));
+        sc.tab[e] = (r < ms) ? expm_fixed64(sc.frx[qq] * (uint64_t)r) : expm_fixed64(sc.fdx[qq] * (uint64_t)(r - ms));
     }
     __syncthreads();
     // stage A: tpr lanes per (receiver, chirp) row, sums over fast time
@@ -198,10 +202,11 @@ __device__ __forceinline__ void moments_group(const Geom& g, const float2* __res
         if (row < rows) {
             const int qq = row / mc, m = row - qq * mc;
             const float2* yr = y + ((size_t)(q0 + qq) * mc + m) * ms;
-            const float2* er = sc.tab + qq * span;
+            const double2* er = sc.tab + qq * span;
 #pragma unroll 8
             for (int s = lane; s < ms; s += tpr) {
-                const float2 v = yr[s], e = er[s];
+                const float2 v = yr[s];
+                const double2 e = er[s];
                 const double re = (double)v.x * e.x - (double)v.y * e.y;
                 const double im = (double)v.x * e.y + (double)v.y * e.x;
                 a0r += re;
@@ -237,7 +242,7 @@ __device__ __forceinline__ void moments_group(const Geom& g, const float2* __res
     for (int i = 0; i < 12; ++i) acc[i] = 0.0;
     if (tid < rows) {
         const int qq = tid / mc, m = tid - qq * mc;
-        const float2 e = sc.tab[qq * span + ms + m];
+        const double2 e = sc.tab[qq * span + ms + m];
         const double dm = (double)m;
         for (int p = 0; p < (full ? 3 : 1); ++p) {
             const double2 a = sc.a[p][tid];
@@ -550,19 +555,20 @@ __global__ __launch_bounds__(kThreads) void refine_single_kernel(Geom g, GridP g
 // together; each barrier wait is bounded regardless (an expired wait aborts the
 // launch's cells, whose estimates are then NaN).
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// C += A B for one 16 x 16 complex tile on the matrix cores (FP32, four real
+// C += A B for one 16 x 16 complex tile on the matrix cores (FP64, four real
 // 16x16x4 products per complex one).  Lane l = r + 16 g holds the contraction
 // indices 8 g + e (e < 8) of row r of A and of column r of B; the output
-// element (i, j) is in lane j + 16 (i / 4), slot i % 4.
-__device__ __forceinline__ void mfma_tile(const float2 (&a)[8], const float2 (&b)[8], f32x4& cre, f32x4& cim) {
+// element (i, j) is in lane j + 16 (i % 4), slot i / 4 (the FP64 instruction's
+// order; its FP32 counterpart keeps four consecutive rows in one lane).
+__device__ __forceinline__ void mfma_tile(const double2 (&a)[8], const double2 (&b)[8], f64x4& cre, f64x4& cim) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e].x, b[e].x, cre, 0, 0, 0);
-        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[e].y, b[e].y, cre, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e].x, b[e].y, cim, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e].y, b[e].x, cim, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f64_16x16x4f64(a[e].x, b[e].x, cre, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[e].y, b[e].y, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a[e].x, b[e].y, cim, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a[e].y, b[e].x, cim, 0, 0, 0);
     }
 }
 
@@ -570,9 +576,10 @@ constexpr int kCT = 512;             // threads of a cluster workgroup
 constexpr int kCand = 8;             // points per pass
 constexpr int kRowsMaxC = kCT / kCand;   // rows per workgroup (one thread per (point, row))
 constexpr int kRowsMinC = kCT / 64;      // at most 64 lanes per row
-constexpr int kInFlight = 32 / kCand;    // frame loads in flight per lane
+constexpr int kCandV = 2;            // points per sweep of a row on the VALU path
+constexpr int kInFlight = 4;         // frame loads in flight per lane
 constexpr int kWgsTarget = 16;       // preferred workgroups per cell
-constexpr int kErMax = 8192;         // range phase factors per pass (64 KB of LDS)
+constexpr int kErMax = 4096;         // range phase factors per pass (64 KB of LDS)
 constexpr int kSlotsMax = 4096;      // workgroups per launch (partial-buffer slots)
 constexpr unsigned kSpinLimit = 1u << 21;
 
@@ -584,8 +591,8 @@ struct Cluster {
 };
 
 struct ClusterShared {
-    float2 ed[kCand][kRowsMaxC];          // Doppler phase factor [point][row]
-    float2 a[kCand][3][kRowsMaxC];        // A_p [point][p][row] (FP32 sums)
+    double2 ed[kCand][kRowsMaxC];         // Doppler phase factor [point][row]
+    double2 a[kCand][3][kRowsMaxC];       // A_p [point][p][row]
     double red[kCand][kRowsMaxC / 8][12]; // per-lane-group partial moments
     double mom[kCand][kMaxRx][12];        // the cell's moments at each point of the pass
     double cur[kMaxRx][12];               // moments at the current point
@@ -593,7 +600,7 @@ struct ClusterShared {
     double tsum[14];
     double th[kCand][4];
     double cand[kCand][4];                // the points in grid-step coordinates
-    uint32_t fr[kCand][kMaxRx], fd[kCand][kMaxRx];
+    uint64_t fr[kCand][kMaxRx], fd[kCand][kMaxRx];
     double step[4];
     int ok;
 };
@@ -640,7 +647,7 @@ __device__ __forceinline__ bool mfma_rows(const Cluster& cl, int ms, const Clust
 // One pass at the points sh.th[0 .. npts): leaves all six moments of every
 // receiver at each point in sh.mom.  er: LDS table of range phase factors.
 __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx& cx, const float2* __restrict__ y,
-                             float2* er, int npts, unsigned& pass, ClusterShared& sh, unsigned* ctr,
+                             double2* er, int npts, unsigned& pass, ClusterShared& sh, unsigned* ctr,
                              unsigned* abort_flag, double* __restrict__ part) {
     const int tid = threadIdx.x;
     const int ms = g.ms, mc = g.mc, R = cl.rows_per_wg;
@@ -648,20 +655,20 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
         const int c = tid / cx.nq, i = tid - c * cx.nq;
         FreqC f;
         freq_compact(g, cx.q_lo + i, sh.th[c], f);
-        sh.fr[c][i] = cycles_to_fixed(f.fr);
-        sh.fd[c][i] = cycles_to_fixed(f.fd);
+        sh.fr[c][i] = cycles_to_fixed64(f.fr);
+        sh.fd[c][i] = cycles_to_fixed64(f.fd);
     }
     __syncthreads();
     const int nte = cx.nq * ms;
     for (int e = tid; e < npts * nte; e += kCT) {
         const int c = e / nte, r = e - c * nte;
         const int i = r >> g.log2_ms, s = r & (ms - 1);
-        er[e] = expm_fixed(sh.fr[c][i] * (uint32_t)s);
+        er[e] = expm_fixed64(sh.fr[c][i] * (uint64_t)s);
     }
     for (int e = tid; e < npts * cx.nrows; e += kCT) {
         const int c = e / cx.nrows, r = e - c * cx.nrows;
         const int gr = cx.r0 + r;
-        sh.ed[c][r] = expm_fixed(sh.fd[c][(gr >> g.log2_mc) - cx.q_lo] * (uint32_t)(gr & (mc - 1)));
+        sh.ed[c][r] = expm_fixed64(sh.fd[c][(gr >> g.log2_mc) - cx.q_lo] * (uint64_t)(gr & (mc - 1)));
     }
     __syncthreads();
     // per row and point: A_p = sum_s s^p Y[row][s] e_r[s]
@@ -677,30 +684,30 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
         const int kparts = ntiles >= kCT / 64 ? 1 : 2;
         const int h = wave / ntiles, t = wave - h * ntiles;
         const bool active = h < kparts;
-        f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+        f64x4 cre = {0.0, 0.0, 0.0, 0.0}, cim = {0.0, 0.0, 0.0, 0.0};
         if (active) {
             const int row = (t >> 1) * 16 + r, col = (t & 1) * 16 + r;
             const int pw = col >> 3, c = col & 7;
             const bool rowv = row < cx.nrows, colv = col < 24 && c < npts;
             const float2* yr = y + (size_t)(cx.r0 + (rowv ? row : 0)) * ms;
-            const float2* ec = er + c * ms;
+            const double2* ec = er + c * ms;
             const int span = ms / kparts;
             for (int s0 = h * span; s0 < (h + 1) * span; s0 += 32) {
                 const int sb = s0 + grp * 8;
-                float2 a[8], b[8];
+                double2 a[8], b[8];
                 const float4* y4 = reinterpret_cast<const float4*>(yr + sb);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const float4 v = rowv ? y4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-                    a[2 * i] = make_float2(v.x, v.y);
-                    a[2 * i + 1] = make_float2(v.z, v.w);
+                    a[2 * i] = make_double2(v.x, v.y);
+                    a[2 * i + 1] = make_double2(v.z, v.w);
                 }
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    const float fs = (float)(sb + e);
-                    const float w = pw == 0 ? 1.f : (pw == 1 ? fs : fs * fs);
-                    const float2 ev = colv ? ec[sb + e] : make_float2(0.f, 0.f);
-                    b[e] = make_float2(ev.x * w, ev.y * w);
+                    const double fs = (double)(sb + e);
+                    const double w = pw == 0 ? 1.0 : (pw == 1 ? fs : fs * fs);
+                    const double2 ev = colv ? ec[sb + e] : make_double2(0.0, 0.0);
+                    b[e] = make_double2(ev.x * w, ev.y * w);
                 }
                 mfma_tile(a, b, cre, cim);
             }
@@ -708,65 +715,69 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
         const int j = (t & 1) * 16 + r, c_out = j & 7, p_out = j >> 3;
         if (active && h == 0 && j < 24) {
 #pragma unroll
-            for (int sl = 0; sl < 4; ++sl) sh.a[c_out][p_out][(t >> 1) * 16 + 4 * grp + sl] = make_float2(cre[sl], cim[sl]);
+            for (int sl = 0; sl < 4; ++sl) sh.a[c_out][p_out][(t >> 1) * 16 + 4 * sl + grp] = make_double2(cre[sl], cim[sl]);
         }
         __syncthreads();
         if (active && h == 1 && j < 24) {
 #pragma unroll
             for (int sl = 0; sl < 4; ++sl) {
-                float2& d = sh.a[c_out][p_out][(t >> 1) * 16 + 4 * grp + sl];
-                d = make_float2(d.x + cre[sl], d.y + cim[sl]);
+                double2& d = sh.a[c_out][p_out][(t >> 1) * 16 + 4 * sl + grp];
+                d = make_double2(d.x + cre[sl], d.y + cim[sl]);
             }
         }
     } else {
-        // on the VALU: FP32 products and sums, tpr lanes per row
+        // on the VALU: FP64 products and sums, tpr lanes per row, kCandV points per sweep of the row
         const int tpr = kCT / R;
         const int row = tid / tpr, lane = tid & (tpr - 1);
-        float acc[kCand][6];
+        for (int c0 = 0; c0 < npts; c0 += kCandV) {
+            double acc[kCandV][6];
 #pragma unroll
-        for (int c = 0; c < kCand; ++c)
+            for (int c = 0; c < kCandV; ++c)
 #pragma unroll
-            for (int i = 0; i < 6; ++i) acc[c][i] = 0.f;
-        if (row < cx.nrows) {
-            const float2* yr = y + (size_t)(cx.r0 + row) * ms;
-            const int eoff = (((cx.r0 + row) >> g.log2_mc) - cx.q_lo) * ms;
-            // kInFlight independent loads per lane, then their products (in sample order)
-            for (int s0 = lane; s0 < ms; s0 += kInFlight * tpr) {
-                float2 v[kInFlight];
+                for (int i = 0; i < 6; ++i) acc[c][i] = 0.0;
+            if (row < cx.nrows) {
+                const float2* yr = y + (size_t)(cx.r0 + row) * ms;
+                const int eoff = (((cx.r0 + row) >> g.log2_mc) - cx.q_lo) * ms;
+                // kInFlight independent loads per lane, then their products (in sample order)
+                for (int s0 = lane; s0 < ms; s0 += kInFlight * tpr) {
+                    float2 v[kInFlight];
 #pragma unroll
-                for (int k = 0; k < kInFlight; ++k) {
-                    const int s = s0 + k * tpr;
-                    v[k] = s < ms ? yr[s] : make_float2(0.f, 0.f);
-                }
+                    for (int k = 0; k < kInFlight; ++k) {
+                        const int s = s0 + k * tpr;
+                        v[k] = s < ms ? yr[s] : make_float2(0.f, 0.f);
+                    }
 #pragma unroll
-                for (int k = 0; k < kInFlight; ++k) {
-                    const int s = s0 + k * tpr;
-                    if (s < ms) {
-                        const float fs = (float)s, fs2 = fs * fs;
+                    for (int k = 0; k < kInFlight; ++k) {
+                        const int s = s0 + k * tpr;
+                        if (s < ms) {
+                            const double fs = (double)s, fs2 = fs * fs;
+                            const double vx = v[k].x, vy = v[k].y;
 #pragma unroll
-                        for (int c = 0; c < kCand; ++c) {
-                            if (c < npts) {
-                                const float2 e = er[c * nte + eoff + s];
-                                const float re = fmaf(v[k].x, e.x, -v[k].y * e.y);
-                                const float im = fmaf(v[k].x, e.y, v[k].y * e.x);
-                                acc[c][0] += re;
-                                acc[c][1] += im;
-                                acc[c][2] = fmaf(re, fs, acc[c][2]);
-                                acc[c][3] = fmaf(im, fs, acc[c][3]);
-                                acc[c][4] = fmaf(re, fs2, acc[c][4]);
-                                acc[c][5] = fmaf(im, fs2, acc[c][5]);
+                            for (int c = 0; c < kCandV; ++c) {
+                                if (c0 + c < npts) {
+                                    const double2 e = er[(c0 + c) * nte + eoff + s];
+                                    const double re = fma(vx, e.x, -vy * e.y);
+                                    const double im = fma(vx, e.y, vy * e.x);
+                                    acc[c][0] += re;
+                                    acc[c][1] += im;
+                                    acc[c][2] = fma(re, fs, acc[c][2]);
+                                    acc[c][3] = fma(im, fs, acc[c][3]);
+                                    acc[c][4] = fma(re, fs2, acc[c][4]);
+                                    acc[c][5] = fma(im, fs2, acc[c][5]);
+                                }
                             }
                         }
                     }
                 }
             }
-        }
-        group_sum_to_first(reinterpret_cast<float(&)[kCand * 6]>(acc), tpr);
-        if (lane == 0) {
+            group_sum_to_first(reinterpret_cast<double(&)[kCandV * 6]>(acc), tpr);
+            if (lane == 0) {
 #pragma unroll
-            for (int c = 0; c < kCand; ++c)
+                for (int c = 0; c < kCandV; ++c)
 #pragma unroll
-                for (int p = 0; p < 3; ++p) sh.a[c][p][row] = make_float2(acc[c][2 * p], acc[c][2 * p + 1]);
+                    for (int p = 0; p < 3; ++p)
+                        if (c0 + c < npts) sh.a[c0 + c][p][row] = make_double2(acc[c][2 * p], acc[c][2 * p + 1]);
+            }
         }
     }
     __syncthreads();
@@ -777,12 +788,11 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
 #pragma unroll
         for (int i = 0; i < 12; ++i) acc[i] = 0.0;
         if (c < npts && row < cx.nrows) {
-            const float2 e = sh.ed[c][row];
+            const double2 e = sh.ed[c][row];
             const double dm = (double)((cx.r0 + row) & (mc - 1));
 #pragma unroll
             for (int p = 0; p < 3; ++p) {
-                const float2 af = sh.a[c][p][row];
-                const double2 a = make_double2(af.x, af.y);
+                const double2 a = sh.a[c][p][row];
                 const double re = a.x * e.x - a.y * e.y;
                 const double im = a.x * e.y + a.y * e.x;
                 if (p == 0) {
@@ -854,9 +864,8 @@ __global__ __launch_bounds__(kCT) void refine_cluster_kernel(Geom g, GridP gp, c
                                                             int max_iter, Cluster cl,
                                                             double* __restrict__ theta_out, unsigned* ctr,
                                                             unsigned* abort_flag, double* part, int* status) {
-    extern __shared__ float4 er4[];                 // range phase factors of one pass
+    extern __shared__ double2 er[];                 // range phase factors of one pass
     __shared__ ClusterShared sh;
-    float2* er = reinterpret_cast<float2*>(er4);
     const int tid = threadIdx.x;
     ClusterCtx cx;
     const int lc = (int)blockIdx.x / cl.wgs;        // cell within the launch
@@ -1019,7 +1028,8 @@ hipError_t launch_refine(const Geom& g, const GridP& gp, const float2* y, const 
     for (int r = rows_pref(g); r <= rows_max(g); r <<= 1) {
         Cluster c = cluster_plan(g, r, ncells);
         const int nq = r <= g.mc ? 1 : r / g.mc;
-        const size_t l = (size_t)kCand * nq * g.ms * sizeof(float2);
+        const size_t l = (size_t)kCand * nq * g.ms * sizeof(double2);
+        if (l > (size_t)kErMax * sizeof(double2)) continue;   // the pass's range table does not fit
         int per_cu = 0;
         if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
                  &per_cu, reinterpret_cast<const void*>(refine_cluster_kernel), kCT, l)) != hipSuccess)
