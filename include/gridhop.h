@@ -10,7 +10,8 @@
  * Conventions shared by every entry point
  *  - Device pointers (prefix d_) are caller-owned HIP device allocations; the
  *    library never allocates device memory (scratch space comes from caller
- *    workspaces whose size the *_workspace_bytes() queries give) and retains
+ *    workspaces whose size the *_workspace_bytes() queries give, or, for
+ *    gh_refine_noalloc alone, from a static device array of the library) and retains
  *    no pointer after returning, except a gh_batch object, which keeps its
  *    frame and workspace pointers until gh_batch_destroy.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
@@ -50,9 +51,11 @@
 extern "C" {
 #endif
 
-#define GH_ABI_VERSION 2
+#define GH_ABI_VERSION 3
 #define GH_MAX_RX 16
 #define GH_MAX_SUPPORT 32
+#define GH_REFINE_NOALLOC_MAX_CELLS 1024              /* cells per gh_refine_noalloc call */
+#define GH_REFINE_NOALLOC_SCRATCH_BYTES (4u << 20)    /* its static device scratch per GPU */
 
 typedef enum {
     GH_OK = 0,
@@ -252,10 +255,28 @@ size_t gh_refine_workspace_bytes(const gh_radar *radar, const gh_grid *grid, int
  * only when other work holds the device's compute units for that long).
  * d_status: int32 [1] out (NULL: not written), the number of such NaN cells
  * (0 when every estimate is valid); read it after synchronising the stream.
- * Moments accumulate in FP32 per chirp and FP64 beyond; fixed-point phases. */
+ * FP64 throughout: phases in 64-bit fixed point (exact modulo one cycle),
+ * phase factors, moments and the Newton solve in FP64. */
 int gh_refine(const gh_radar *radar, const gh_grid *grid, const void *d_y, const int64_t *d_cells,
               int32_t n_cells, int32_t max_iter, void *d_ws, size_t ws_bytes, double *d_theta,
               int32_t *d_status, void *stream);
+
+/* gh_refine for callers that cannot allocate device memory or own a workspace
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same refinement and results, with the scratch (barrier
+ * counters and partial moments) taken from a static device array of
+ * GH_REFINE_NOALLOC_SCRATCH_BYTES inside the library instead of d_ws.  Every
+ * GPU the library runs this on holds one such array until the process ends.
+ * Allocates nothing and calls no allocating routine; it clears what must
+ * start at zero with a kernel, so it can be captured.  Cells that need more
+ * partial-moment slots at once than the array holds are refined by several
+ * launches.  n_cells: 0..GH_REFINE_NOALLOC_MAX_CELLS (more: GH_EUNSUPPORTED,
+ * nothing enqueued); other arguments as gh_refine.  Every call on one GPU
+ * shares that GPU's array: calls that may overlap in time on one GPU (other
+ * streams, other threads, other processes' contexts excepted) race and give
+ * undefined results; serialise them (one stream, or events). */
+int gh_refine_noalloc(const gh_radar *radar, const gh_grid *grid, const void *d_y, const int64_t *d_cells,
+                      int32_t n_cells, int32_t max_iter, double *d_theta, int32_t *d_status, void *stream);
 
 /* Decisions at continuous points, with gradients (differentiation axis; not
  * in the paper).  For each point theta = (x, y, vx, vy) (d_theta: double

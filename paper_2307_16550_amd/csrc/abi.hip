@@ -446,6 +446,27 @@ int gh_bomp_fit(const gh_radar* radar, const gh_grid* grid, const void* d_y, voi
     return ok();
 }
 
+int gh_refine_noalloc(const gh_radar* radar, const gh_grid* grid, const void* d_y, const int64_t* d_cells,
+                      int32_t n_cells, int32_t max_iter, double* d_theta, int32_t* d_status, void* stream) {
+    gh::Geom g;
+    gh::GridP gp;
+    int rc = make_geom(radar, g);
+    if (rc || (rc = make_grid(grid, gp))) return rc;
+    if (!d_y || !d_cells || !d_theta) return fail(GH_EINVAL, "NULL device pointer");
+    if ((rc = check_aligned({d_y, d_cells, d_theta, d_status}))) return rc;
+    if (n_cells < 0) return fail(GH_EINVAL, "n_cells must be non-negative");
+    if (n_cells > GH_REFINE_NOALLOC_MAX_CELLS)
+        return fail(GH_EUNSUPPORTED, "gh_refine_noalloc takes at most %d cells (got %d); use gh_refine",
+                    GH_REFINE_NOALLOC_MAX_CELLS, n_cells);
+    if (max_iter < 1 || max_iter > 100) return fail(GH_EINVAL, "max_iter must be in [1, 100]");
+    if (n_cells == 0) return ok();
+    if ((rc = check_device())) return rc;
+    hipError_t e = gh::launch_refine_noalloc(g, gp, (const float2*)d_y, d_cells, n_cells, max_iter, d_theta, d_status,
+                                             (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gh_refine_noalloc launch");
+    return ok();
+}
+
 size_t gh_refine_workspace_bytes(const gh_radar* radar, const gh_grid* grid, int32_t n_cells) {
     gh::Geom g;
     gh::GridP gp;

@@ -369,6 +369,10 @@ size_t refine_ws_bytes(const Geom& g, int ncells);
 // (a cluster barrier wait expired).
 hipError_t launch_refine(const Geom& g, const GridP& gp, const float2* y, const int64_t* cells, int ncells,
                          int max_iter, void* ws, double* theta, int* status, hipStream_t st);
+// The same with the library's own static scratch (gh_refine_noalloc): no
+// allocation; ncells <= GH_REFINE_NOALLOC_MAX_CELLS.
+hipError_t launch_refine_noalloc(const Geom& g, const GridP& gp, const float2* y, const int64_t* cells, int ncells,
+                                 int max_iter, double* theta, int* status, hipStream_t st);
 
 size_t direct_points_ws_bytes(const Geom& g, int npts);
 hipError_t launch_direct_points(const Geom& g, const float2* y, const double* theta, int npts, void* ws,

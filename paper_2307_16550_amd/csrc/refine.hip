@@ -27,6 +27,8 @@
 // is halved until the decision does not decrease (at most 16 candidates).
 // The answer is the converged local maximum of D on the box.
 
+#include <mutex>
+
 #include "gh_internal.h"
 #include "lane_sum.h"
 
@@ -1011,15 +1013,20 @@ size_t refine_ws_bytes(const Geom& g, int ncells) {
     return counters_bytes(ncells) + 2 * (size_t)cl.slots * kCand * kMaxRx * 12 * sizeof(double);
 }
 
-hipError_t launch_refine(const Geom& g, const GridP& gp, const float2* y, const int64_t* cells, int ncells,
-                         int max_iter, void* ws, double* theta, int* status, hipStream_t st) {
+namespace {
+
+// The launches of one refinement call.  ws: the barrier counters of ncells
+// cells and the abort flag (counters_bytes(ncells)), then slots_cap
+// partial-buffer slots; cells that need more slots at once than that are
+// refined by several launches.
+hipError_t launch_refine_slots(const Geom& g, const GridP& gp, const float2* y, const int64_t* cells, int ncells,
+                               int max_iter, void* ws, int slots_cap, double* theta, int* status, hipStream_t st) {
     // the one-workgroup-per-cell kernel when the test switch asks for it
     const bool single_only = knob(GH_KNOB_REFINE_SINGLE) != 0;
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    const int slots_cap = cluster_plan(g, kRowsMinC, ncells).slots;   // as sized by refine_ws_bytes
     // preferred rows per workgroup, doubled while the cells need more than one launch
     Cluster cl{};
     long capacity = 0;
@@ -1077,6 +1084,62 @@ hipError_t launch_refine(const Geom& g, const GridP& gp, const float2* y, const 
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_refine(const Geom& g, const GridP& gp, const float2* y, const int64_t* cells, int ncells,
+                         int max_iter, void* ws, double* theta, int* status, hipStream_t st) {
+    // the slots refine_ws_bytes sized the workspace for
+    return launch_refine_slots(g, gp, y, cells, ncells, max_iter, ws, cluster_plan(g, kRowsMinC, ncells).slots,
+                               theta, status, st);
+}
+
+// ---- refinement without allocation -----------------------------------------
+// Scratch of gh_refine_noalloc: the counters of at most
+// GH_REFINE_NOALLOC_MAX_CELLS cells and the abort flag, then as many
+// partial-buffer slots (two parities of kCand x kMaxRx x 12 doubles each) as
+// the rest holds.  Every device the library runs on holds one copy, at its own
+// address, until the process ends; every call on a device shares it.
+constexpr size_t kNoAllocBytes = GH_REFINE_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+
+constexpr size_t kSlotBytes = 2 * (size_t)kCand * kMaxRx * 12 * sizeof(double);
+
+// Device address of the current device's scratch (looked up once per device).
+hipError_t noalloc_scratch(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void* p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_refine_noalloc(const Geom& g, const GridP& gp, const float2* y, const int64_t* cells, int ncells,
+                                 int max_iter, double* theta, int* status, hipStream_t st) {
+    void* ws = nullptr;
+    hipError_t e = noalloc_scratch(&ws);
+    if (e != hipSuccess) return e;
+    // counters first, partials after counters_bytes(ncells) <= counters_bytes(max cells)
+    static_assert(kNoAllocBytes > ((size_t)GH_REFINE_NOALLOC_MAX_CELLS + 1) * sizeof(unsigned) + 256 + 64 * kSlotBytes,
+                  "the scratch must hold the counters and at least 64 partial-buffer slots");
+    const int slots = (int)((kNoAllocBytes - counters_bytes(GH_REFINE_NOALLOC_MAX_CELLS)) / kSlotBytes);
+    return launch_refine_slots(g, gp, y, cells, ncells, max_iter, ws, slots, theta, status, st);
 }
 
 }  // namespace gh

@@ -27,7 +27,7 @@ MAX_SUPPORT = 32
 EXPORTS = ("gh_abi_version", "gh_last_error", "gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_workspace_bytes",
            "gh_direct_decision", "gh_bomp_workspace_bytes", "gh_bomp_step", "gh_bomp_select", "gh_bomp_fit",
            "gh_refine_workspace_bytes",
-           "gh_refine", "gh_direct_points_workspace_bytes", "gh_direct_points", "gh_gh_points",
+           "gh_refine", "gh_refine_noalloc", "gh_direct_points_workspace_bytes", "gh_direct_points", "gh_gh_points",
            "gh_range_spectra", "gh_factored_workspace_bytes", "gh_factored_decision",
            "gh_batch_workspace_bytes", "gh_batch_create", "gh_batch_tune", "gh_batch_get_info", "gh_batch_run",
            "gh_batch_frame_maps", "gh_batch_destroy", "gh_test_set_knob")
@@ -95,6 +95,7 @@ def load():
     lib.gh_refine_workspace_bytes.argtypes = [rp, gp_, i32]
     lib.gh_refine_workspace_bytes.restype = sz
     lib.gh_refine.argtypes = [rp, gp_, vp, vp, i32, i32, vp, sz, vp, vp, vp]
+    lib.gh_refine_noalloc.argtypes = [rp, gp_, vp, vp, i32, i32, vp, vp, vp]
     lib.gh_test_set_knob.argtypes = [i32, i32]
     lib.gh_test_set_knob.restype = ctypes.c_int
     lib.gh_direct_points_workspace_bytes.argtypes = [rp, i32]
@@ -116,7 +117,7 @@ def load():
     lib.gh_batch_destroy.argtypes = [vp]
     lib.gh_batch_destroy.restype = None
     for name in ("gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_decision", "gh_bomp_step", "gh_bomp_select",
-                 "gh_bomp_fit", "gh_refine",
+                 "gh_bomp_fit", "gh_refine", "gh_refine_noalloc",
                  "gh_direct_points", "gh_gh_points", "gh_range_spectra", "gh_factored_decision", "gh_batch_create", "gh_batch_tune", "gh_batch_get_info",
                  "gh_batch_run", "gh_batch_frame_maps"):
         getattr(lib, name).restype = ctypes.c_int
@@ -367,6 +368,25 @@ def refine(radar: Radar, grid: GhGrid, y, cells: torch.Tensor, max_iter=20, thet
         raise ValueError("status must be an int32 CUDA tensor with at least one element")
     _check(lib.gh_refine(ctypes.byref(radar.c_struct), ctypes.byref(grid), _ptr(y), _ptr(cells), cells.numel(),
                          int(max_iter), _ptr(ws), nws, _ptr(theta), _ptr(status), _stream(stream)))
+    return theta
+
+
+REFINE_NOALLOC_MAX_CELLS = 1024
+
+
+def refine_noalloc(radar: Radar, grid: GhGrid, y, cells: torch.Tensor, max_iter=20, theta=None, status=None,
+                   stream=None):
+    """gh_refine_noalloc: as refine(), with the library's static scratch (no workspace)."""
+    lib = load()
+    _c64(y)
+    if cells.dtype != torch.int64 or not cells.is_cuda:
+        raise ValueError("cells must be an int64 CUDA tensor")
+    if theta is None:
+        theta = torch.empty((cells.numel(), 4), dtype=torch.float64, device=y.device)
+    if status is not None and (status.dtype != torch.int32 or not status.is_cuda or status.numel() < 1):
+        raise ValueError("status must be an int32 CUDA tensor with at least one element")
+    _check(lib.gh_refine_noalloc(ctypes.byref(radar.c_struct), ctypes.byref(grid), _ptr(y), _ptr(cells),
+                                 cells.numel(), int(max_iter), _ptr(theta), _ptr(status), _stream(stream)))
     return theta
 
 

@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.gh_abi_version() == 2
+    assert lib.gh_abi_version() == 3
 
 
 def radar(**kw):
@@ -121,6 +121,29 @@ def test_bomp_and_refine_argument_checks(lib):
     assert lib.gh_refine(*rargs, 3, 20, None, rws, FAKE, None, None) == gh.GH_EINVAL
     assert lib.gh_refine(*rargs, 3, 20, FAKE, rws, FAKE, ctypes.c_void_p(0x1004), None) == gh.GH_EINVAL  # status misaligned
     assert lib.gh_refine(*rargs, 0, 20, None, 0, FAKE, None, None) == gh.GH_OK
+
+
+def test_refine_noalloc_argument_checks(lib):
+    """The no-allocation refinement rejects more cells than its static scratch
+    serves, and the arguments gh_refine rejects, before touching a device."""
+    r = radar()
+    rargs = [ctypes.byref(r.c_struct), ctypes.byref(GRID), FAKE, FAKE]
+    assert lib.gh_refine_noalloc(*rargs, gh.REFINE_NOALLOC_MAX_CELLS + 1, 20, FAKE, None, None) == gh.GH_EUNSUPPORTED
+    assert "at most 1024 cells" in gh.last_error()
+    assert lib.gh_refine_noalloc(*rargs, -1, 20, FAKE, None, None) == gh.GH_EINVAL
+    assert lib.gh_refine_noalloc(*rargs, 3, 0, FAKE, None, None) == gh.GH_EINVAL                # max_iter 0
+    assert lib.gh_refine_noalloc(*rargs, 3, 101, FAKE, None, None) == gh.GH_EINVAL
+    assert lib.gh_refine_noalloc(*rargs, 3, 20, None, None, None) == gh.GH_EINVAL               # theta NULL
+    assert lib.gh_refine_noalloc(*rargs, 3, 20, FAKE, ctypes.c_void_p(0x1004), None) == gh.GH_EINVAL
+    assert lib.gh_refine_noalloc(ctypes.byref(r.c_struct), ctypes.byref(GRID), None, FAKE, 3, 20, FAKE, None,
+                                 None) == gh.GH_EINVAL
+    assert lib.gh_refine_noalloc(*rargs, 0, 20, FAKE, None, None) == gh.GH_OK
+
+
+def test_header_limits_of_refine_noalloc():
+    text = open(os.path.join(ROOT, "include", "gridhop.h")).read()
+    assert re.search(r"#define GH_REFINE_NOALLOC_MAX_CELLS (\d+)", text).group(1) == str(gh.REFINE_NOALLOC_MAX_CELLS)
+    assert "#define GH_REFINE_NOALLOC_SCRATCH_BYTES (4u << 20)" in text
 
 
 def test_bomp_select_and_fit_argument_checks(lib):
