@@ -169,6 +169,33 @@ __device__ __forceinline__ void wave_peak(float& v, int& i) {
     }
 }
 
+// The same maximum on the VALU alone (no LDS round trips, which queue behind
+// a sweep's table traffic): within each row of 16 lanes, merges with the row
+// rotated by 1, 2, 4 and 8 lanes (DPP row_ror), then the four row results by
+// lane reads.  Every lane ends with the wave's maximum.  All 64 lanes must be
+// active.
+template <int CTRL>
+__device__ __forceinline__ void peak_merge_dpp(float& v, int& i) {
+    const float v2 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+    const int i2 = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xf, 0xf, false);
+    peak_merge(v, i, v2, i2);
+}
+
+__device__ __forceinline__ void wave_peak_rows(float& v, int& i) {
+    peak_merge_dpp<0x121>(v, i);   // row_ror:1
+    peak_merge_dpp<0x122>(v, i);   // row_ror:2
+    peak_merge_dpp<0x124>(v, i);   // row_ror:4
+    peak_merge_dpp<0x128>(v, i);   // row_ror:8
+    float rv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    int ri = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+    for (int r = 1; r < 4; ++r)
+        peak_merge(rv, ri, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16 * r)),
+                   __builtin_amdgcn_readlane(i, 16 * r));
+    v = rv;
+    i = ri;
+}
+
 // Per-location epilogue shared by the decision kernels: write the slab (if
 // `dec`), reduce its maximum (ties -> lowest index) skipping excluded cells,
 // and store the block peak.  `acc[j]` holds the value of point tid + j*NT.

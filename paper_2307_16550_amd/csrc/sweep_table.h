@@ -27,6 +27,39 @@ struct FastGeo {
     uint32_t pad;
 };
 
+// 1 / sqrt(v) in FP64 for v >= 0: the hardware estimate refined by two Newton
+// steps (relative error at the level of FP64 rounding); 0 for v == 0, which
+// makes the unit vector of a zero-length leg zero.
+__device__ __forceinline__ double rsqrt_fp64(double v) {
+    if (!(v > 0.0)) return 0.0;
+    const double h = 0.5 * v;
+    double y = __builtin_amdgcn_rsq(v);
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
+// The bistatic range R and the sum w of the two unit vectors (eqs. (1)-(2)),
+// FP64, with one reciprocal square root per leg instead of a square root and
+// two divisions.
+__device__ __forceinline__ void bistatic_rsq(const Geom& g, int q, double x, double y, double& r, double& wx,
+                                             double& wy) {
+    const double dx0 = x - g.tx[0], dy0 = y - g.tx[1];
+    const double dx1 = x - g.rx[q][0], dy1 = y - g.rx[q][1];
+    const double s0 = fma(dx0, dx0, dy0 * dy0), s1 = fma(dx1, dx1, dy1 * dy1);
+    const double i0 = rsqrt_fp64(s0), i1 = rsqrt_fp64(s1);
+    r = fma(s0, i0, s1 * i1);
+    wx = fma(dx0, i0, dx1 * i1);
+    wy = fma(dy0, i0, dy1 * i1);
+}
+
+// cycles_to_fixed without the 64-bit integer conversion: the rounded value
+// lies in [0, 2^32], and 2^32 wraps to 0.
+__device__ __forceinline__ uint32_t cycles_to_fixed32(double cyc) {
+    const double s = fma(cyc - floor(cyc), 4294967296.0, 0.5);
+    return s >= 4294967296.0 ? 0u : (uint32_t)s;
+}
+
 // Geometry of location `lc` (row-major over (x, y)) and receiver q; a zero
 // record when lc is past the grid.  inv = 1 / P.
 template <int INTERP>
@@ -43,7 +76,7 @@ __device__ __forceinline__ FastGeo fast_geo(const Geom& g, const GridP& gp, int 
     if (lc < gp.nloc) {
         const int ix = lc / gp.n[1], iy = lc - ix * gp.n[1];
         double r, wx, wy;
-        bistatic(g, q, gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], r, wx, wy);
+        bistatic_rsq(g, q, gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], r, wx, wy);
         const double tr = g.kr * r;
         const double fl = floor(tr);
         const float a = (float)(tr - fl);
@@ -66,9 +99,9 @@ __device__ __forceinline__ FastGeo fast_geo(const Geom& g, const GridP& gp, int 
             fg.row[u] = ((uint32_t)(row & (g.nr - 1)) << g.log2_nd) * (uint32_t)es;
             fg.w[u] = (((row >> g.log2_nr) & 1) ? g.sign_r * w[u] : w[u]) * scale;
         }
-        fg.t0 = cycles_to_fixed(g.kd * (wx * gp.lo[2] + wy * gp.lo[3]) * inv);
-        fg.ax = cycles_to_fixed_step(g.kd * wx * gp.step[2] * inv);
-        fg.ay = cycles_to_fixed_step(g.kd * wy * gp.step[3] * inv);
+        fg.t0 = cycles_to_fixed32(g.kd * (wx * gp.lo[2] + wy * gp.lo[3]) * inv);
+        fg.ax = cycles_to_fixed32(g.kd * wx * gp.step[2] * inv);
+        fg.ay = cycles_to_fixed32(g.kd * wy * gp.step[3] * inv);
     }
     return fg;
 }
@@ -125,6 +158,62 @@ __device__ __forceinline__ void table_store_prefetched(float4* tab, const Prefet
             tab[l0] = make_float4(h0.x - d0.x, h0.y - d0.y, d0.x, d0.y);
             tab[l0 + 1] = make_float4(h1.x - d1.x, h1.y - d1.y, d1.x, d1.y);
         }
+    }
+}
+
+// Bilinear tables of N_d = 128 NCH entries without guards: lane i builds the
+// entry pairs (2 i + 128 c, 2 i + 1 + 128 c), c < NCH, from one vector load per
+// map row and pair.  The profile value that follows a pair comes from lane
+// i + 1 by a wave rotation (DPP); lane 63 takes lane 0's first value of the
+// next chunk, or for the last chunk of the row's start with the sign of the
+// next period.  Row offsets and weights are wave-uniform; per-chunk offsets
+// are immediates.  The next receiver's values are prefetched into registers
+// while the current table is evaluated.
+template <int NCH>
+struct PrefetchN {
+    float4 a[NCH], b[NCH];
+};
+
+// o_lane: lane * 2 * (bytes per map value).
+template <int DT, int NCH>
+__device__ __forceinline__ void table_prefetch_n(PrefetchN<NCH>& pf, const char* mq, uint32_t r0, uint32_t r1,
+                                                 uint32_t o_lane) {
+    constexpr uint32_t kEs = map_elem_bytes(DT);
+    const char* m0 = mq + r0;
+    const char* m1 = mq + r1;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const uint32_t o0 = o_lane + (uint32_t)c * 128u * kEs;
+        pf.a[c] = map_ld2<DT>(m0, o0);
+        pf.b[c] = map_ld2<DT>(m1, o0);
+    }
+}
+
+// Lane i receives lane (i + 1) mod 64's value (DPP wave_rol:1; all lanes active).
+__device__ __forceinline__ float from_next_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xf, 0xf, false));
+}
+
+// tab: this lane's first pair (the wave's table + 2 lane entries).
+template <int NCH>
+__device__ __forceinline__ void table_store_n(float4* tab, const PrefetchN<NCH>& pf, float w0, float w1,
+                                              bool last_lane, float sd) {
+    float2 h0[NCH], h1[NCH], nx[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        h0[c] = wsum2(w0, make_float2(pf.a[c].x, pf.a[c].y), w1, make_float2(pf.b[c].x, pf.b[c].y));
+        h1[c] = wsum2(w0, make_float2(pf.a[c].z, pf.a[c].w), w1, make_float2(pf.b[c].z, pf.b[c].w));
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) nx[c] = make_float2(from_next_lane(h0[c].x), from_next_lane(h0[c].y));
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const float2 wrap = (c == NCH - 1) ? make_float2(nx[0].x * sd, nx[0].y * sd) : nx[(c + 1) % NCH];
+        const float2 h2 = last_lane ? wrap : nx[c];
+        const float2 d0 = make_float2(h1[c].x - h0[c].x, h1[c].y - h0[c].y);
+        const float2 d1 = make_float2(h2.x - h1[c].x, h2.y - h1[c].y);
+        tab[128 * c] = make_float4(h0[c].x - d0.x, h0[c].y - d0.y, d0.x, d0.y);
+        tab[128 * c + 1] = make_float4(h1[c].x - d1.x, h1[c].y - d1.y, d1.x, d1.y);
     }
 }
 
@@ -222,6 +311,9 @@ __device__ __forceinline__ void eval_column(float (&acc)[NVX], const float4* tab
             if (INTERP) e1[u] = tab[bin * kEntry + 1];
             t += ax;
         }
+        // issue the batch's reads before any of its arithmetic (the scheduler
+        // would otherwise keep two in flight to save registers)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
             float re, im;
