@@ -108,14 +108,15 @@ def top_peaks(block: torch.Tensor, grid: gh.GhGrid, k=16, radius=(4, 4, 2, 2)):
     return np.array(chosen, dtype=np.int64)
 
 
-def ascend(value_grad, theta0: torch.Tensor, h, steps=20, step0=0.25, grow=1.5):
+def ascend(value_grad, theta0: torch.Tensor, h, steps=20, step0=0.25, grow=1.5, return_accepted=False):
     """Monotone gradient ascent of a decision at n points, `steps` iterations.
 
     value_grad(theta) -> (value [n], grad [n, 4]).  Coordinates are scaled by the
     grid steps h (an axis with h = 0 is held).  Each iteration proposes
     z + s * g_z / max|g_z| (s in grid steps, per point), accepts it when the
     decision does not decrease (then s *= grow) and otherwise halves s.
-    Returns (theta, value, history of values [steps + 1, n]).
+    Returns (theta, value, history of values [steps + 1, n]), and with
+    return_accepted also the acceptance of each proposal (bool [steps, n]).
     """
     h_t = torch.as_tensor(np.asarray(h, np.float64), device=theta0.device)
     free = h_t > 0
@@ -123,6 +124,7 @@ def ascend(value_grad, theta0: torch.Tensor, h, steps=20, step0=0.25, grow=1.5):
     value, grad = value_grad(theta)
     s = torch.full((theta.shape[0],), float(step0), dtype=torch.float64, device=theta.device)
     hist = [value.clone()]
+    accepted = []
     for _ in range(steps):
         gz = torch.where(free, grad * h_t, torch.zeros_like(grad))
         norm = gz.abs().amax(dim=1).clamp_min(1e-300)
@@ -134,4 +136,7 @@ def ascend(value_grad, theta0: torch.Tensor, h, steps=20, step0=0.25, grow=1.5):
         grad = torch.where(ok[:, None], g_new, grad)
         s = torch.where(ok, s * grow, s * 0.5)
         hist.append(value.clone())
+        accepted.append(ok)
+    if return_accepted:
+        return theta, value, torch.stack(hist), torch.stack(accepted)
     return theta, value, torch.stack(hist)

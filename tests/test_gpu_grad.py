@@ -211,3 +211,127 @@ def test_top_peaks_and_gradient_ascent_cfg5():
         for th, gg in ((th0[i], g0[i]), (th1[i], gfin[i])):
             _, rg, _ = ograd.direct_value_grad(s.y, r, th)
             assert np.max(np.abs(gg.cpu().numpy() - rg)) <= 1e-4 * scale
+
+
+def _oracle_replay(value_grad64, theta0, h, accepted, step0=0.25, grow=1.5):
+    """The ascent of ag.ascend for one point in FP64 with the oracle's gradient,
+    taking the GPU's accept/reject decisions (so the two walks see the same
+    step lengths and differ only by their gradient arithmetic)."""
+    free = h > 0
+    theta = np.array(theta0, np.float64)
+    _, grad = value_grad64(theta)
+    s = step0
+    for ok in accepted:
+        gz = np.where(free, grad * h, 0.0)
+        cand = theta + (s / max(np.abs(gz).max(), 1e-300)) * gz * h
+        if ok:
+            theta = cand
+            _, grad = value_grad64(theta)
+            s *= grow
+        else:
+            s *= 0.5
+    return theta
+
+
+@pytest.mark.parametrize("interp", [gh.BILINEAR, gh.BICUBIC])
+def test_gh_gradient_ascent_cfg5(interp):
+    """Differentiation workload: the top-16 grid-hopping peaks climbed for 20 steps
+    through the adjoint of the grid-hopping decision (GhDecisionAt, torch.autograd);
+    three of them replayed in FP64 with the oracle's analytic gradient on the FP64
+    maps must land within 1e-3 m and 1e-3 m/s of the GPU walk."""
+    say(f"gh ascent cfg5 interp={interp}")
+    s, r, gr = scene_and_radar(5)
+    y = to_dev(s.y)
+    g = gh.grid_of(s.grid)
+    z = gh.rd_maps(gr, y)
+    _, block, _ = gh.decision(gr, g, z, interp, write_volume=False)
+    cells = ag.top_peaks(block, g, 16)
+    theta0 = to_dev(ag.cell_points(g, cells))
+
+    def vg(th):
+        th = th.detach().clone().requires_grad_(True)
+        v = ag.gh_decision_at(th, gr, z, interp)
+        v.sum().backward()
+        return v.detach(), th.grad.detach()
+
+    h = ag.grid_steps(g)
+    theta, value, hist, acc = ag.ascend(vg, theta0, h, steps=20, return_accepted=True)
+    hist, acc = hist.cpu().numpy(), acc.cpu().numpy()
+    assert np.all(np.diff(hist, axis=0) >= 0.0)
+    assert np.sum(hist[-1] > hist[0]) >= 14
+    zr = omaps.rd_maps(s.y, r.pad_r, r.pad_d, r.centered)
+    vg64 = lambda th: ograd.gh_value_grad(zr, r, th, interp)[:2]
+    th0, th1 = theta0.cpu().numpy(), theta.cpu().numpy()
+    for i in range(3):
+        ref = _oracle_replay(vg64, th0[i], h, acc[:, i])
+        dp, dv = np.max(np.abs(th1[i, :2] - ref[:2])), np.max(np.abs(th1[i, 2:] - ref[2:]))
+        say(f"peak {i}: {int(acc[:, i].sum())} accepted steps, |dpos| {dp:.3g} m, |dvel| {dv:.3g} m/s")
+        assert dp <= 1e-3 and dv <= 1e-3
+
+
+def test_autograd_finite_differences_cfg5():
+    """Differentiation workload: both autograd functions at points near the targets of
+    the 8-receiver frame against central differences (h = 1e-4) of the GPU forward
+    and against the FP64 analytic gradient (the grid-hopping decision with Keys
+    maps, whose weights are differentiable; bilinear has kinks at map nodes)."""
+    s, r, gr = scene_and_radar(5)
+    y = to_dev(s.y)
+    z = gh.rd_maps(gr, y)
+    zr = omaps.rd_maps(s.y, r.pad_r, r.pad_d, r.centered)
+    pts = points_near_targets(s, 8, 21)
+    hfd = 1e-4
+    for name, fwd, ref in (
+            ("direct", lambda th: ag.direct_decision_at(th, gr, y), lambda p: ograd.direct_value_grad(s.y, r, p)),
+            ("gh bicubic", lambda th: ag.gh_decision_at(th, gr, z, gh.BICUBIC),
+             lambda p: ograd.gh_value_grad(zr, r, p, gh.BICUBIC))):
+        theta = to_dev(pts).requires_grad_(True)
+        d = fwd(theta)
+        d.sum().backward()
+        gt = theta.grad.cpu().numpy()
+        scale = np.abs(gt).max()
+        rg = np.stack([ref(p)[1] for p in pts])
+        ea = np.max(np.abs(gt - rg)) / np.abs(rg).max()
+        say(f"{name} cfg5: autograd vs FP64 analytic {ea:.3g}")
+        assert ea <= 1e-4
+        with torch.no_grad():
+            for a in range(4):
+                e = torch.zeros(4, dtype=torch.float64, device=dev())
+                e[a] = hfd
+                fd = ((fwd(theta + e) - fwd(theta - e)) / (2 * hfd)).cpu().numpy()
+                err = np.max(np.abs(fd - gt[:, a])) / scale
+                say(f"{name} cfg5: d/dtheta_{a} central-difference error {err:.3g}")
+                assert err <= 1e-2
+
+
+def test_rx_calibration_gradient_cfg5():
+    """Differentiation workload: the 8 receivers displaced by a seeded +-5 cm; at each
+    target the GPU receiver gradient (direct decision, and grid hopping on Keys maps of
+    the nominal array) matches the FP64 analytic one, and a small step of the receiver
+    positions along it raises the direct decision."""
+    s, r, gr = scene_and_radar(5)
+    rng = np.random.default_rng(5505)
+    off = rng.uniform(-0.05, 0.05, gr.rx.shape)
+    gr_off = gr.with_rx(gr.rx + off)
+    r_off = ord_.radar_from_scene(s)
+    r_off.rx = r_off.rx + off
+    y = to_dev(s.y)
+    truth = np.concatenate([s.pos, s.vel], axis=1)
+    v, _, grx = gh.direct_points(gr_off, y, to_dev(truth), want_grad_rx=True)
+    grx = grx.cpu().numpy()
+    for t in range(truth.shape[0]):
+        _, _, rgx = ograd.direct_value_grad(s.y, r_off, truth[t])
+        err = np.max(np.abs(grx[t] - rgx)) / np.abs(rgx).max()
+        assert err <= 1e-4, (t, err)
+    say(f"rx calibration cfg5 (direct): {truth.shape[0]} targets within 1e-4")
+    step = 1e-3 * grx[0] / np.abs(grx[0]).max()
+    v2, _, _ = gh.direct_points(gr_off.with_rx(gr_off.rx + step), y, to_dev(truth[:1]), want_grad=False)
+    assert float(v2[0]) > float(v[0])
+    z = gh.rd_maps(gr, y)
+    zr = omaps.rd_maps(s.y, r.pad_r, r.pad_d, r.centered)
+    _, _, gxg = gh.gh_points(gr_off, z, to_dev(truth), gh.BICUBIC, want_grad_rx=True)
+    gxg = gxg.cpu().numpy()
+    for t in range(truth.shape[0]):
+        _, _, rgx = ograd.gh_value_grad(zr, r_off, truth[t], gh.BICUBIC)
+        err = np.max(np.abs(gxg[t] - rgx)) / np.abs(rgx).max()
+        assert err <= 1e-4, (t, err)
+    say(f"rx calibration cfg5 (grid hopping, bicubic): {truth.shape[0]} targets within 1e-4")
