@@ -10,21 +10,23 @@ synchronisation inside the step:
      (16,777,216 points), FP32 volume written, block maxima, global argmax;
   3. direct decision on the stride-2 64 x 64 x 16 x 16 subgrid (1,048,576
      points), volume written, block maxima, global argmax;
-  4. Block-OMP, 3 iterations (each: maps of the residual (by FFT of the
-     frame in the first, from the maps of the frame and the fitted atoms in
-     closed form after it), grid-hopping argmax-only sweep with the support
-     excluded, least-squares fit, residual);
+  4. Block-OMP, 3 iterations: the first selection is the argmax of step 2
+     (gh_bomp_seed: the maps of step 1 are the run's maps of the frame, and
+     its decision is the first selection's sweep), then per iteration the
+     least-squares fit and residual, and for the next selection the maps of
+     the residual (from the maps of the frame and the fitted atoms in closed
+     form) and a grid-hopping argmax-only sweep with the support excluded;
   5. Newton refinement of the 3 selected cells.
-Grid points evaluated per step: 4 x 16,777,216 (grid hopping) + 1,048,576
-(direct).  `value` is that count divided by the measured step time.  The
-step is captured once in a HIP graph (kernel launches only; no memset) and
-the timed steps are graph replays.  Rows 1-2, row 3 and rows 4-5 are three
-independent chains: by default (`--streams 2`) row 3 and the maps of row 1
-run on a second stream beside the Block-OMP iterations, and the rest of rows
-1-2 (after the last Block-OMP fit, which the refinement does not need) on
-that stream beside the refinement; the second stream is forked from and
-joined back into the capture stream.  `--streams 1` captures everything on
-one stream in the order above.  The per-row times come from eager
+Grid points evaluated per step: 3 x 16,777,216 (grid hopping: the sweep of
+step 2 and the two later selections) + 1,048,576 (direct).  `value` is that
+count divided by the measured step time.  The step is captured once in a
+HIP graph (kernel launches only; no memset) and the timed steps are graph
+replays.  Row 3 is independent of the rest: by default (`--streams 2`) it
+runs on a second stream beside rows 1, 2 and 4, and the last Block-OMP fit
+(which the refinement does not need) runs there beside the refinement; the
+second stream is forked from and joined back into the capture stream.
+`--streams 1` captures everything on one stream in the order above.  The
+per-row times come from eager
 one-stream steps with HIP events, and after the replays the step's outputs
 (argmax cells, Block-OMP support and coefficients, refined estimates) are
 compared with those of an eager step (`graph_matches_eager`).
@@ -57,6 +59,9 @@ sys.path.insert(0, ROOT)
 
 CFG = 2
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FLOP_PER_POINT_RX = {"bilinear": 12, "bicubic": 44}   # algorithmic, per grid point and receiver
+PRECISION_CFG = 3
 CUS = 256                 # MI355X compute units
 CLOCK_HZ = 2.4e9          # peak engine clock
 BOMP_ITERS = 3
@@ -193,12 +198,15 @@ def cpu_worker(path, parallel=False):
     t_ref1 = time.perf_counter() - t0
 
     n_gh, n_dir = grid.size, dgrid.size
-    t_step = (1 + BOMP_ITERS) * (t_maps + n_gh * t_gh_pt) + n_dir * t_dir_pt + t_fit + len(support) * t_ref1
+    # the step's work: maps of the frame and of the residual before each later
+    # selection, BOMP_ITERS sweeps of the grid, the direct subgrid, the fits and
+    # the refinement of every selected cell
+    t_step = BOMP_ITERS * (t_maps + n_gh * t_gh_pt) + n_dir * t_dir_pt + t_fit + len(support) * t_ref1
     sampled = t_maps + len(gh_idx) * t_gh_pt + len(d_idx) * t_dir_pt + t_fit + t_ref1
     gh_scale = max(float(np.max(gh_ref)), float(job["gh_max"]))
     dir_scale = max(float(np.max(dir_ref)), float(job["dir_max"]))
     out = {
-        "value": ((1 + BOMP_ITERS) * n_gh + n_dir) / t_step,
+        "value": (BOMP_ITERS * n_gh + n_dir) / t_step,
         "unit": "grid points/s",
         "cores": cores,
         "kind": "oracle",
@@ -337,6 +345,7 @@ def main():
     dblock = gh.peaks_tensor(nloc_d, dev)
     darg = gh.peaks_tensor(1, dev)
     bomp = gh.BompState(radar, grid, y, max_support=BOMP_ITERS, use_direct=False, interp=interp)
+    fmaps = bomp.maps       # the frame's maps: the grid-hopping row's and Block-OMP's
     theta = torch.empty((BOMP_ITERS, 4), dtype=torch.float64, device=dev)
     rws = torch.empty(gh.refine_workspace_bytes(radar, grid, BOMP_ITERS), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
@@ -350,10 +359,10 @@ def main():
         e = [ev() for _ in range(6)] if record else None
         if record:
             e[0].record(stream)
-        gh.rd_maps(radar, y, maps)
+        gh.rd_maps(radar, y, fmaps)
         if record:
             e[1].record(stream)
-        gh.decision(radar, grid, maps, interp, dec=dec, block=block, want_argmax=False)
+        gh.decision(radar, grid, fmaps, interp, dec=dec, block=block, want_argmax=False)
         if record:
             e[2].record(stream)
         gh.argmax(block, arg)
@@ -364,7 +373,9 @@ def main():
             e[4].record(stream)
         gh.argmax(dblock, darg)
         bomp.reset()
-        for _ in range(BOMP_ITERS):
+        bomp.seed(arg)
+        bomp.fit()
+        for _ in range(BOMP_ITERS - 1):
             bomp.step()
         gh.refine(radar, grid, y, bomp.support, theta=theta, ws=rws)
         if record:
@@ -381,14 +392,13 @@ def main():
     snap = lambda: [t.clone() for t in (arg, darg, bomp.support, bomp.alpha, theta)]
     ref = snap()
 
-    # The rows form three independent chains: (A) maps, sweep, argmax; (B) the
-    # direct decision and its argmax; (C) Block-OMP and the refinement, which
-    # rebuild their own maps from their own residual.  With two streams, C runs
-    # on the capture stream; a second stream (default priority), forked from
-    # and joined back into it, runs B and the maps of A beside the Block-OMP
-    # iterations, then, once the last selection is made, the last fit (the
-    # refinement needs only the selections) and the rest of A beside the
-    # latency-bound refinement.
+    # The direct decision (B) is independent of the chain maps -> sweep ->
+    # argmax -> Block-OMP -> refinement (A; the sweep is Block-OMP's first
+    # selection).  With two streams, A runs on the capture stream; a second
+    # stream (default priority), forked from and joined back into it, runs B
+    # beside it, then, once the last selection is made, the last fit (the
+    # refinement needs only the selections) beside the latency-bound
+    # refinement.
     side = torch.cuda.Stream(device=dev) if args.streams == 2 else None
 
     def step_two_streams():
@@ -399,9 +409,13 @@ def main():
         with torch.cuda.stream(side):
             gh.direct_decision(radar, dgrid, y, ws=ws, dec=ddec, block=dblock, want_argmax=False)
             gh.argmax(dblock, darg)
-            gh.rd_maps(radar, y, maps)
+        gh.rd_maps(radar, y, fmaps)
+        gh.decision(radar, grid, fmaps, interp, dec=dec, block=block, want_argmax=False)
+        gh.argmax(block, arg)
         bomp.reset()
-        for _ in range(BOMP_ITERS - 1):
+        bomp.seed(arg)
+        bomp.fit()
+        for _ in range(BOMP_ITERS - 2):
             bomp.step()
         bomp.select()
         selected = torch.cuda.Event()
@@ -409,8 +423,6 @@ def main():
         side.wait_event(selected)
         with torch.cuda.stream(side):
             bomp.fit()
-            gh.decision(radar, grid, maps, interp, dec=dec, block=block, want_argmax=False)
-            gh.argmax(block, arg)
         gh.refine(radar, grid, y, bomp.support, theta=theta, ws=rws)
         join.record(side)
         main_s.wait_event(join)
@@ -494,6 +506,38 @@ def main():
         torch.cuda.synchronize()
         t_gh_sub = s0.elapsed_time(s1) * 1e-3 / 20
 
+        # the selection sweep alone: argmax only (no volume), the frame's maps, no exclusions
+        sel_block = gh.peaks_tensor(nloc, dev)
+        for _ in range(3):
+            gh.decision(radar, grid, fmaps, interp, block=sel_block, write_volume=False, want_argmax=False)
+        a0, a1 = ev(), ev()
+        a0.record(stream)
+        for _ in range(20):
+            gh.decision(radar, grid, fmaps, interp, block=sel_block, write_volume=False, want_argmax=False)
+        a1.record(stream)
+        torch.cuda.synchronize()
+        t_sel = a0.elapsed_time(a1) * 1e-3 / 20
+
+        # the precision workload's sweep (K = 8, 256 x 256 x 32 x 32, complex64 maps): its
+        # 268 MB volume is larger than the 256 MB Infinity Cache
+        s3 = sc.make_scene(PRECISION_CFG, 0)
+        r3 = gh.Radar.from_scene(s3)
+        g3 = gh.grid_of(s3.grid)
+        z3 = gh.rd_maps(r3, torch.from_numpy(s3.y).to(dev))
+        dec3 = torch.empty(tuple(s3.grid.n), dtype=torch.float32, device=dev)
+        blk3 = gh.peaks_tensor(s3.grid.n[0] * s3.grid.n[1], dev)
+        for _ in range(3):
+            gh.decision(r3, g3, z3, interp, dec=dec3, block=blk3, want_argmax=False)
+        p0, p1 = ev(), ev()
+        p0.record(stream)
+        for _ in range(10):
+            gh.decision(r3, g3, z3, interp, dec=dec3, block=blk3, want_argmax=False)
+        p1.record(stream)
+        torch.cuda.synchronize()
+        t3 = p0.elapsed_time(p1) * 1e-3 / 10
+        bytes3 = 4 * s3.grid.size + z3.numel() * 8 + 16 * blk3.shape[0]
+        del dec3, z3
+
         # the direct decision with BF16 matrix-core operands, timed on its own (not part of the step)
         ws_b = torch.empty(gh.direct_workspace_bytes(radar, dgrid, gh.GEMM_BF16), dtype=torch.uint8, device=dev)
         ddec_b = torch.empty_like(ddec)
@@ -514,11 +558,13 @@ def main():
             "t_gh_sub": t_gh_sub,
             "t_dir_bf16": t_dir_bf16,
             "err_bf16": err_bf16,
+            "t_sel": t_sel,
+            "precision": {"t": t3, "bytes": bytes3, "points": s3.grid.size, "k": r3.k},
             "factored": factored_timings(gh, torch, radar, grid, y, stream),
         }
 
     ms_step = wall / args.steps * 1e3
-    pts_step = (1 + BOMP_ITERS) * n_gh + n_dir
+    pts_step = BOMP_ITERS * n_gh + n_dir     # the sweep of step 2 is the first selection's
     sweep_bytes = 4 * n_gh + radar.k * radar.nr * radar.nd * 8 + 16 * nloc
     achieved = sweep_bytes / t_sweep / 1e9
 
@@ -579,6 +625,21 @@ def main():
             "factored": x["factored"],
         })
         line["roofline"]["frac_of_copy"] = achieved / x["copy_gbs"]
+        # the Block-OMP selection sweeps write no volume: no HBM bytes to speak of;
+        # their algorithmic FP32 work against the vector peak
+        flops_sel = FLOP_PER_POINT_RX[args.interp] * radar.k * n_gh
+        line["selection_sweep"] = {"avg_launch_us": x["t_sel"] * 1e6, "points_per_s": n_gh / x["t_sel"],
+                                   "bound": "alu", "achieved": flops_sel / x["t_sel"] / 1e12,
+                                   "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": flops_sel / x["t_sel"] / 1e12 / FP32_PEAK_TFLOPS,
+                                   "flop_per_point_rx": FLOP_PER_POINT_RX[args.interp]}
+        p = x["precision"]
+        ach3 = p["bytes"] / p["t"] / 1e9
+        line["roofline_precision_frame"] = {
+            "kernel": line["roofline"]["kernel"], "workload": "K=8, Ms=64 x Mc=32, grid 256x256x32x32, volume written",
+            "bound": "hbm", "achieved": ach3, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach3 / HBM_PEAK_GBS,
+            "traffic": None, "algorithmic_bytes_per_launch": p["bytes"], "avg_launch_us": p["t"] * 1e6,
+            "points_per_s": p["points"] / p["t"], "frac_of_copy": ach3 / x["copy_gbs"]}
     if not args.no_batch and not args.step_only:
         line["batch"] = batch_workload(gh, sc, torch, stream)
 

@@ -220,6 +220,22 @@ int gh_bomp_select(const gh_radar *radar, const gh_grid *grid, const void *d_y, 
                    int32_t n_support, int32_t max_support, gh_peak *d_selected, void *d_ws, size_t ws_bytes,
                    void *stream);
 
+/* Steps 1 and 2 of gh_bomp_step at n_support == 0 (grid hopping) taken from a
+ * grid-hopping decision the caller has already made on the frame itself, so
+ * that a caller who needs both that decision (its volume, say) and Block-OMP
+ * computes the frame's maps and the first sweep once.  Preconditions (the
+ * caller's): the run's d_maps holds gh_rd_maps of d_y (complex64), the buffer
+ * later passed to gh_bomp_select / gh_bomp_step, and d_argmax holds the
+ * gh_decision (or gh_argmax) maximum over the same grid with the same interp,
+ * computed from those maps.  Writes d_support[0] = d_argmax->index and, when
+ * d_selected is non-NULL, *d_selected = *d_argmax, and readies d_ws (of
+ * gh_bomp_workspace_bytes(radar, grid, 0, any gemm_dtype) bytes) for the later
+ * selections.  The run then continues with gh_bomp_fit(n_selected = 1).
+ * max_support and interp as in gh_bomp_step. */
+int gh_bomp_seed(const gh_radar *radar, const gh_grid *grid, int32_t interp, const gh_peak *d_argmax,
+                 int64_t *d_support, int32_t max_support, gh_peak *d_selected, void *d_ws, size_t ws_bytes,
+                 void *stream);
+
 /* Steps 3 and 4 of gh_bomp_step alone: least squares over the n_selected
  * cells d_support[0 .. n_selected) (1 <= n_selected <= max_support <=
  * GH_MAX_SUPPORT), alpha (complex64 [n_selected][K]) to d_alpha, and

@@ -25,7 +25,7 @@ MAP_C64, MAP_F16, MAP_BF16 = 0, 1, 2
 MAX_SUPPORT = 32
 
 EXPORTS = ("gh_abi_version", "gh_last_error", "gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_workspace_bytes",
-           "gh_direct_decision", "gh_bomp_workspace_bytes", "gh_bomp_step", "gh_bomp_select", "gh_bomp_fit",
+           "gh_direct_decision", "gh_bomp_workspace_bytes", "gh_bomp_step", "gh_bomp_select", "gh_bomp_seed", "gh_bomp_fit",
            "gh_refine_workspace_bytes",
            "gh_refine", "gh_refine_noalloc", "gh_direct_points_workspace_bytes", "gh_direct_points", "gh_gh_points",
            "gh_range_spectra", "gh_factored_workspace_bytes", "gh_factored_decision",
@@ -92,6 +92,7 @@ def load():
     lib.gh_bomp_step.argtypes = [rp, gp_, vp, vp, vp, i32, i32, i32, vp, i32, i32, vp, pp, vp, sz, vp]
     lib.gh_bomp_select.argtypes = [rp, gp_, vp, vp, vp, i32, i32, i32, vp, i32, i32, pp, vp, sz, vp]
     lib.gh_bomp_fit.argtypes = [rp, gp_, vp, vp, vp, i32, i32, vp, vp, sz, vp]
+    lib.gh_bomp_seed.argtypes = [rp, gp_, i32, pp, vp, i32, pp, vp, sz, vp]
     lib.gh_refine_workspace_bytes.argtypes = [rp, gp_, i32]
     lib.gh_refine_workspace_bytes.restype = sz
     lib.gh_refine.argtypes = [rp, gp_, vp, vp, i32, i32, vp, sz, vp, vp, vp]
@@ -117,7 +118,7 @@ def load():
     lib.gh_batch_destroy.argtypes = [vp]
     lib.gh_batch_destroy.restype = None
     for name in ("gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_decision", "gh_bomp_step", "gh_bomp_select",
-                 "gh_bomp_fit", "gh_refine", "gh_refine_noalloc",
+                 "gh_bomp_seed", "gh_bomp_fit", "gh_refine", "gh_refine_noalloc",
                  "gh_direct_points", "gh_gh_points", "gh_range_spectra", "gh_factored_decision", "gh_batch_create", "gh_batch_tune", "gh_batch_get_info",
                  "gh_batch_run", "gh_batch_frame_maps"):
         getattr(lib, name).restype = ctypes.c_int
@@ -330,6 +331,21 @@ class BompState:
                                   _ptr(self.resid), _ptr(self.maps), self.use_direct, self.interp, self.gemm,
                                   _ptr(self.support), self.n, self.max_support, _ptr(self.selected),
                                   _ptr(self.ws), self.ws.numel(), _stream(stream)))
+        self._selected_pending = True
+
+    def seed(self, argmax, stream=None):
+        """The first selection from a grid-hopping maximum already computed on the frame
+        (gh_bomp_seed): self.maps must hold rd_maps of y and `argmax` the decision's
+        maximum over the same grid with the same interp.  fit() completes the iteration."""
+        if self.use_direct:
+            raise ValueError("seed() applies to grid-hopping runs")
+        if self._selected_pending:
+            raise RuntimeError("seed() called twice without fit()")
+        lib = load()
+        _check(lib.gh_bomp_seed(ctypes.byref(self.radar.c_struct), ctypes.byref(self.grid), self.interp,
+                                _ptr(argmax), _ptr(self.support), self.max_support, _ptr(self.selected),
+                                _ptr(self.ws), self.ws.numel(), _stream(stream)))
+        self.n = 0
         self._selected_pending = True
 
     def fit(self, stream=None):

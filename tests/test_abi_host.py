@@ -146,6 +146,17 @@ def test_header_limits_of_refine_noalloc():
     assert "#define GH_REFINE_NOALLOC_SCRATCH_BYTES (4u << 20)" in text
 
 
+def test_bomp_seed_argument_checks(lib):
+    r = radar()
+    ws = lib.gh_bomp_workspace_bytes(ctypes.byref(r.c_struct), ctypes.byref(GRID), 0, 0)
+    args = [ctypes.byref(r.c_struct), ctypes.byref(GRID)]
+    assert lib.gh_bomp_seed(*args, 0, FAKE, FAKE, 3, None, FAKE, ws - 1, None) == gh.GH_EWORKSPACE
+    assert lib.gh_bomp_seed(*args, 0, None, FAKE, 3, None, FAKE, ws, None) == gh.GH_EINVAL        # no argmax
+    assert lib.gh_bomp_seed(*args, 0, FAKE, FAKE, 33, None, FAKE, ws, None) == gh.GH_EINVAL       # max_support
+    assert lib.gh_bomp_seed(*args, 5, FAKE, FAKE, 3, None, FAKE, ws, None) == gh.GH_EINVAL        # interp
+    assert lib.gh_bomp_seed(*args, 0, FAKE, ctypes.c_void_p(0x1004), 3, None, FAKE, ws, None) == gh.GH_EINVAL
+
+
 def test_bomp_select_and_fit_argument_checks(lib):
     r = radar()
     ws = lib.gh_bomp_workspace_bytes(ctypes.byref(r.c_struct), ctypes.byref(GRID), 0, 0)

@@ -380,6 +380,34 @@ def test_bomp_many_atoms_closed_form_matches_fft():
     assert torch.equal(a.alpha, b.alpha)
 
 
+@pytest.mark.parametrize("interp", [gh.BILINEAR, gh.BICUBIC])
+def test_bomp_seeded_from_the_decision(interp):
+    """gh_bomp_seed: the grid-hopping decision on the frame's own maps (volume
+    written) and its argmax stand in for Block-OMP's first selection; the run
+    then gives exactly the support, coefficients and residual of three
+    gh_bomp_step calls, on the paper-scale frame."""
+    say(f"bomp seeded cfg=2 interp={interp}")
+    s, r, gr = scene_and_radar(2, 0)
+    grid = gh.grid_of(s.grid)
+    y = to_dev(s.y)
+    a = gh.BompState(gr, grid, y, max_support=3, interp=interp)
+    for _ in range(3):
+        a.step()
+    b = gh.BompState(gr, grid, y, max_support=3, interp=interp)
+    gh.rd_maps(gr, y, b.maps)
+    dec, block, arg = gh.decision(gr, grid, b.maps, interp)
+    b.seed(arg)
+    b.fit()
+    for _ in range(2):
+        b.step()
+    torch.cuda.synchronize()
+    say(f"  support {a.support.cpu().tolist()} / {b.support.cpu().tolist()}")
+    assert torch.equal(a.support, b.support)
+    assert torch.equal(a.alpha, b.alpha)
+    assert torch.equal(a.resid, b.resid)
+    assert int(gh.decode_peaks(b.selected)[1][0]) == int(b.support[2].cpu())
+
+
 def test_bomp_fit_cfg2_full_size():
     """The bench step's three Block-OMP selections on the paper-scale frame, each
     against the oracle's maximum over the whole grid on the oracle's own FP64
