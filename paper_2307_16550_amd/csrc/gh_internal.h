@@ -141,6 +141,18 @@ __host__ __device__ __forceinline__ float map_scale(int ms, int mc, int dt) {
     return dt == GH_MAP_C64 ? 1.f : (float)ms * (float)mc;
 }
 
+// 1 / sqrt(v) in FP64 for v >= 0: the hardware estimate refined by two Newton
+// steps (relative error at the level of FP64 rounding); 0 for v == 0, which
+// makes the unit vector of a zero-length leg zero.
+__device__ __forceinline__ double rsqrt_fp64(double v) {
+    if (!(v > 0.0)) return 0.0;
+    const double h = 0.5 * v;
+    double y = __builtin_amdgcn_rsq(v);
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
 // Bistatic geometry of one location and receiver, FP64.
 __device__ __forceinline__ void bistatic(const Geom& g, int q, double x, double y, double& r, double& wx,
                                          double& wy) {
@@ -236,10 +248,14 @@ __device__ __forceinline__ void slab_epilogue(const float (&acc)[NPTS], int nv, 
 // Largest of n block maxima (ties to the lowest index), reduced by a whole
 // workgroup of up to 1024 threads; the result is valid in thread 0.  red_v and
 // red_i are LDS arrays of blockDim.x / 64 entries.
+// Maximum (ties to the lowest index) of n block peaks by the whole workgroup
+// (every lane active); the result is in thread 0.  Linear grid indices fit in
+// 32 bits (grids have fewer than 2^31 points), so the merges across lanes are
+// the VALU-only wave_peak_rows: per wave, then over the waves' results by wave 0.
 __device__ __forceinline__ void reduce_block_peaks(const gh_peak* __restrict__ blk, int n, float& bv, long long& bi,
                                                    float* red_v, long long* red_i) {
     bv = -INFINITY;
-    bi = 0x7fffffffffffffffLL;
+    int b32 = 0x7fffffff;
     // sixteen independent loads in flight per thread, then their comparisons
     for (int b0 = threadIdx.x; b0 < n; b0 += 16 * blockDim.x) {
         gh_peak p[16];
@@ -251,35 +267,23 @@ __device__ __forceinline__ void reduce_block_peaks(const gh_peak* __restrict__ b
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             const int b = b0 + k * (int)blockDim.x;
-            if (b < n && (p[k].value > bv || (p[k].value == bv && p[k].index < bi))) {
-                bv = p[k].value;
-                bi = p[k].index;
-            }
+            if (b < n) peak_merge(bv, b32, p[k].value, (int)p[k].index);
         }
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const float v2 = __shfl_xor(bv, off, 64);
-        const long long i2 = __shfl_xor(bi, off, 64);
-        if (v2 > bv || (v2 == bv && i2 < bi)) {
-            bv = v2;
-            bi = i2;
-        }
-    }
-    const int wid = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
+    wave_peak_rows(bv, b32);
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
         red_v[wid] = bv;
-        red_i[wid] = bi;
+        red_i[wid] = b32;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
-            if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bi)) {
-                bv = red_v[w];
-                bi = red_i[w];
-            }
-        }
+    if (wid == 0) {
+        const int nw = (int)(blockDim.x >> 6);
+        bv = lane < nw ? red_v[lane] : -INFINITY;
+        b32 = lane < nw ? (int)red_i[lane] : 0x7fffffff;
+        wave_peak_rows(bv, b32);
     }
+    bi = b32;
 }
 
 // Exclusion list entries that fall in this location's slab (thread 0 only).

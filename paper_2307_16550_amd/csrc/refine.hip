@@ -76,9 +76,11 @@ __device__ __forceinline__ void freq_compact(const Geom& g, int q, const double 
         const double ax = leg ? g.rx[q][0] : g.tx[0];
         const double ay = leg ? g.rx[q][1] : g.tx[1];
         const double d0 = th[0] - ax, d1 = th[1] - ay;
-        const double rho = sqrt(d0 * d0 + d1 * d1);
-        if (rho == 0.0) continue;
-        const double u0 = d0 / rho, u1 = d1 / rho, inv = 1.0 / rho, inv2 = inv * inv;
+        const double s2 = fma(d0, d0, d1 * d1);
+        if (s2 == 0.0) continue;
+        const double inv = rsqrt_fp64(s2), inv2 = inv * inv;   // 1 / rho, one reciprocal square root per leg
+        const double rho = s2 * inv;
+        const double u0 = d0 * inv, u1 = d1 * inv;
         const double uv = u0 * v0 + u1 * v1;
         rsum += rho;
         w0 += u0;
@@ -369,7 +371,9 @@ __device__ __forceinline__ void newton_solve(const double t[14], const double h[
         push[a] = h[a] > 0.0 && ((z[a] >= 1.0 - eps && gz[a] > 0.0) || (z[a] <= -1.0 + eps && gz[a] < 0.0));
         mov[a] = h[a] > 0.0 && !push[a];
     }
-    // Cholesky of -H on the moving axes (any other axis gets a unit row and no gradient)
+    // Cholesky of -H on the moving axes (any other axis gets a unit row and no
+    // gradient; its pivot is not part of the definiteness test, whose scale is
+    // the moving axes' largest diagonal entry)
     double l[4][4], dmax = 0.0;
     bool spd = true;
 #pragma unroll
@@ -377,13 +381,14 @@ __device__ __forceinline__ void newton_solve(const double t[14], const double h[
 #pragma unroll
         for (int b = 0; b < 4; ++b) l[a][b] = (mov[a] && mov[b]) ? -hz[a][b] : (a == b ? 1.0 : 0.0);
 #pragma unroll
-    for (int a = 0; a < 4; ++a) dmax = fmax(dmax, fabs(l[a][a]));
+    for (int a = 0; a < 4; ++a)
+        if (mov[a]) dmax = fmax(dmax, fabs(l[a][a]));
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         double d = l[j][j];
 #pragma unroll
         for (int k2 = 0; k2 < j; ++k2) d -= l[j][k2] * l[j][k2];
-        spd = spd && d > 1e-10 * dmax;
+        spd = spd && (!mov[j] || d > 1e-10 * dmax);
         const double ljj = sqrt(fmax(d, 1e-300));
         l[j][j] = ljj;
 #pragma unroll
@@ -580,7 +585,7 @@ constexpr int kRowsMaxC = kCT / kCand;   // rows per workgroup (one thread per (
 constexpr int kRowsMinC = kCT / 64;      // at most 64 lanes per row
 constexpr int kCandV = 2;            // points per sweep of a row on the VALU path
 constexpr int kInFlight = 4;         // frame loads in flight per lane
-constexpr int kWgsTarget = 16;       // preferred workgroups per cell
+constexpr int kWgsTarget = 32;       // preferred workgroups per cell
 constexpr int kErMax = 4096;         // range phase factors per pass (64 KB of LDS)
 constexpr int kSlotsMax = 4096;      // workgroups per launch (partial-buffer slots)
 constexpr unsigned kSpinLimit = 1u << 21;

@@ -27,18 +27,6 @@ struct FastGeo {
     uint32_t pad;
 };
 
-// 1 / sqrt(v) in FP64 for v >= 0: the hardware estimate refined by two Newton
-// steps (relative error at the level of FP64 rounding); 0 for v == 0, which
-// makes the unit vector of a zero-length leg zero.
-__device__ __forceinline__ double rsqrt_fp64(double v) {
-    if (!(v > 0.0)) return 0.0;
-    const double h = 0.5 * v;
-    double y = __builtin_amdgcn_rsq(v);
-    y = y * fma(-h * y, y, 1.5);
-    y = y * fma(-h * y, y, 1.5);
-    return y;
-}
-
 // The bistatic range R and the sum w of the two unit vectors (eqs. (1)-(2)),
 // FP64, with one reciprocal square root per leg instead of a square root and
 // two divisions.
