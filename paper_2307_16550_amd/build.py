@@ -28,6 +28,9 @@ COMPILE_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
+# per-source additions: the direct decision keeps its matrix-core accumulators in
+# VGPRs (without this the BF16 loops copy them between AGPRs every step)
+FILE_FLAGS = {"direct.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 LINK_FLAGS = ["--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,-rpath,/opt/rocm/lib"]
 
 
@@ -47,7 +50,8 @@ def build(verbose: bool = False, extra=None, jobs: int | None = None) -> str:
         for src in sources():
             obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
             objs.append(obj)
-            cmds.append([HIPCC, *COMPILE_FLAGS, *(extra or []), *inc, "-c", src, "-o", obj])
+            cmds.append([HIPCC, *COMPILE_FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), *(extra or []), *inc, "-c",
+                         src, "-o", obj])
         if verbose:
             for c in cmds:
                 print(" ".join(c), flush=True)

@@ -13,16 +13,21 @@
 //
 // Matrix-core mapping (64-lane wave, 16 x 16 output tile, FP32 accumulation):
 //   lane = r + 16 g holds contraction indices k0 + 8 g + e (e = 0..7) of row r
-//   of the left operand and of column r of the right operand.  BF16 issues
-//   one 16x16x32 product per real part pairing; FP32 issues eight 16x16x4
-//   products, the e-th taking element e of every lane (any assignment of
-//   contraction indices to the k slots is valid if both operands share it).
-//   The output element (i, j) sits in lane j + 16 (i / 4), slot i % 4.
-// A complex product is four real ones:
-//   Re C += Re A Re B - Im A Im B,  Im C += Re A Im B + Im A Re B.
-// Atoms are generated in registers: one exact anchor per run of eight from a
+//   of the left operand and of column r of the right operand.  FP32 issues
+//   eight 16x16x4 products, the e-th taking element e of every lane (any
+//   assignment of contraction indices to the k slots is valid if both
+//   operands share it).  The output element (i, j) sits in lane j + 16 (i / 4),
+//   slot i % 4.
+// FP32: a complex product is four real ones,
+//   Re C += Re A Re B - Im A Im B,  Im C += Re A Im B + Im A Re B;
+// atoms are generated in registers: one exact anchor per run of eight from a
 // 32-bit fixed-point phase (the wrap modulo one cycle is integer overflow),
 // then the recurrence e_{n+1} = e_n exp(-j 2 pi f).
+// BF16 (gemm_dtype BF16): complex products over interleaved (re, im) pairs,
+// two 16x16x32 products per complex tile step; the range zoom stages the frame
+// in LDS once per workgroup and leaves h = G times a chirp in BF16; the Doppler
+// zoom reads its left operand from a chirp (Toeplitz) table and forms its
+// right one from h and a second chirp table (see the kernels below).
 #include "gh_internal.h"
 
 namespace gh {
@@ -145,100 +150,208 @@ __global__ __launch_bounds__(kThreads) void direct_range_zoom(Geom g, GridP gp, 
     }
 }
 
-// Range zoom with BF16 operands: as below, but the four waves share the frame
-// operand: each 32-sample step of the 64 chirps is staged once in LDS
-// (double-buffered, rows padded to an odd number of 16-byte words so the
-// operand reads do not conflict) instead of being read from L2 by every wave.
-// BF16 products are cheap enough that those L2 reads bound the kernel (71 ->
-// 53 us for the BF16 direct decision of the paper-scale subgrid); in FP32 the
-// staging gains 2 us and its 35 KB of LDS cost more beside other kernels.
-constexpr int kYRows = 16 * kNT;                 // chirps per workgroup
-constexpr int kYRow4 = 32 / 2 + 1;              // float4 per staged row: 32 samples + padding
+// ---- BF16 operands ----------------------------------------------------------
+// A complex product as real ones over interleaved (re, im) pairs: contraction
+// slot 2k + c of a 16x16x32 BF16 product holds the real (c = 0) or imaginary
+// (c = 1) part of complex index k, so one product contracts 16 complex
+// indices.  With the right operand b laid out (br, bi) per index and the left
+// one in the two forms (ar, -ai) and (ai, ar),
+//   Re(a b) = ar br - ai bi   and   Im(a b) = ai br + ar bi
+// take two products instead of four.  Lane r + 16 g holds complex indices
+// 4 g .. 4 g + 3 of row r (left operand) or column r (right operand).
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((fvec2){lo, hi}, bf16x2));
+}
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+__device__ __forceinline__ bf16x2 as_bf16x2(uint32_t v) { return __builtin_bit_cast(bf16x2, v); }
+
+// BF16 dot product of two (x, y) pairs with an FP32 result, a.x b.x + a.y b.y
+__device__ __forceinline__ float dot2_bf16(uint32_t a, uint32_t b) {
+    return __builtin_amdgcn_fdot2_f32_bf16(as_bf16x2(a), as_bf16x2(b), 0.f, false);
+}
+
+struct ToepPlan {
+    int ex, ey, mcp, words;   // table lengths and 32-bit words per receiver
+};
+
+__host__ __device__ inline ToepPlan toep_plan(int mc, int nvx, int nvy) {
+    ToepPlan p;
+    p.mcp = mc < 16 ? 16 : mc;
+    p.ex = (p.mcp + ((nvx + 15) & ~15) - 1 + 3) & ~3;
+    p.ey = (p.mcp + ((nvy + 15) & ~15) - 1 + 3) & ~3;
+    p.words = 2 * p.ex + 2 * p.ey + p.mcp;
+    return p;
+}
+
+// exp(-j 2 pi ph 2^-32) from the hardware sine and cosine (argument in revolutions)
+__device__ __forceinline__ float2 expm_hw(uint32_t ph) {
+    const float x = __uint2float_rn(ph) * 2.3283064365386963e-10f;   // 2^-32
+    return make_float2(__builtin_amdgcn_cosf(x), -__builtin_amdgcn_sinf(x));
+}
+
+// High word of (a * b) mod 2^64 for a 64-bit fixed-point a and a 32-bit integer b.
+__device__ __forceinline__ uint32_t fixed_mul_hi(uint64_t a, uint32_t b) {
+    return (uint32_t)(a >> 32) * b + __umulhi((uint32_t)a, b);
+}
+
+
+// Range zoom with BF16 operands.  A workgroup owns 64 LT locations x 16 CT
+// chirps of one receiver; wave w owns locations 16 LT w .. 16 LT (w + 1) - 1.
+// The frame's chirps are staged in LDS as BF16 pairs, 64 samples at a time
+// (double-buffered; rows padded by 16 bytes so the operand reads of 16 rows
+// fall in distinct banks), once for the four waves.  Each lane keeps the
+// atoms of its locations at its four sample slots in FP32 and advances them
+// by exp(-j 2 pi 16 f_r) per 16-sample step, rounding to BF16 only as
+// operands.
+//   CHIRP = false: G_q[x][m] (complex64 [K][Nloc][Mc]), as the FP32 path.
+//   CHIRP = true:  h_q[x][m] = G_q[x][m] exp(-j 2 pi (f0 m + (fx + fy) m^2 / 2))
+//                  as BF16 pairs ([K][Nloc][mcp] 32-bit words, mcp = max(Mc, 16);
+//                  words m >= Mc are not written), the right-hand factor of
+//                  the chirp-table Doppler zoom below.
+constexpr int kRzChunk = 64;                 // samples per staged chunk
+constexpr int kRzRowWords = kRzChunk + 4;    // BF16 pairs per staged row (+16 bytes)
+
+template <int LT, int CT, bool CHIRP>
 __global__ __launch_bounds__(kThreads) void direct_range_zoom_bf16(Geom g, GridP gp, const float2* __restrict__ y,
-                                                                  float2* __restrict__ gws) {
-    constexpr bool BF16 = true;
-    __shared__ float4 ytile[2][kYRows][kYRow4];
+                                                                  void* __restrict__ out) {
+    constexpr int kRows = 16 * CT;                 // chirps per workgroup
+    constexpr int kTpr = kThreads / kRows;         // staging threads per row
+    constexpr int kSpt = kRzChunk / kTpr;          // samples per staging thread (4 CT)
+    __shared__ __attribute__((aligned(16))) uint32_t ys[2][kRows * kRzRowWords];
     const int lane = threadIdx.x & 63;
     const int r = lane & 15;
     const int seg = lane >> 4;
     const int q = blockIdx.z;
-    const int loc0 = (blockIdx.x * kWaves + (threadIdx.x >> 6)) * 16;
-    const int m0 = blockIdx.y * kYRows;
+    const int loc0 = (blockIdx.x * kWaves + (threadIdx.x >> 6)) * 16 * LT;
+    const int m0 = blockIdx.y * kRows;
     const int ms = g.ms, mc = g.mc;
+    const int chunk = ms < kRzChunk ? ms : kRzChunk;
+    const int ksteps = (chunk + 15) >> 4;
 
-    uint32_t fr = 0;
-    if (loc0 + r < gp.nloc) {
-        const int loc = loc0 + r;
-        const int ix = loc / gp.n[1], iy = loc - ix * gp.n[1];
-        double rr, wx, wy;
-        bistatic(g, q, gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], rr, wx, wy);
-        fr = cycles_to_fixed(g.fr_per_m * rr);
+    // location 16 lt + r: atoms at samples 4 seg .. 4 seg + 3, the 16-sample step
+    // factor, and (CHIRP) the Doppler chirp rates in 64-bit fixed point
+    float2 at[LT][4], rho[LT];
+    uint64_t f0l[LT], hsl[LT];
+#pragma unroll
+    for (int lt = 0; lt < LT; ++lt) {
+        uint32_t fr = 0;
+        f0l[lt] = hsl[lt] = 0;
+        const int loc = loc0 + 16 * lt + r;
+        if (loc < gp.nloc) {
+            const int ix = loc / gp.n[1], iy = loc - ix * gp.n[1];
+            double rr, wx, wy;
+            bistatic(g, q, gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], rr, wx, wy);
+            fr = cycles_to_fixed(g.fr_per_m * rr);
+            if constexpr (CHIRP) {
+                f0l[lt] = cycles_to_fixed64(g.fd_per_mps * (wx * gp.lo[2] + wy * gp.lo[3]));
+                hsl[lt] = cycles_to_fixed64(0.5 * g.fd_per_mps * (wx * gp.step[2] + wy * gp.step[3]));
+            }
+        }
+        const float2 r1 = expm_fixed(fr);
+        at[lt][0] = expm_fixed(fr * (uint32_t)(4 * seg));
+#pragma unroll
+        for (int e = 1; e < 4; ++e) at[lt][e] = cmul(at[lt][e - 1], r1);
+        rho[lt] = expm_fixed(fr * 16u);
     }
-    const float2 ratio = expm_fixed(fr);
 
-    f32x4 cre[kNT], cim[kNT];
+    f32x4 cre[LT][CT], cim[LT][CT];
 #pragma unroll
-    for (int t = 0; t < kNT; ++t) cre[t] = cim[t] = zero4();
+    for (int lt = 0; lt < LT; ++lt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) cre[lt][ct] = cim[lt][ct] = zero4();
 
-    // staging: 64 rows x 16 float4 (32 samples) per step, four float4 per thread
-    const float4* yq4 = reinterpret_cast<const float4*>(y + (size_t)q * mc * ms);
-    constexpr int kPer = kYRows * 16 / kThreads;
-    float4 stage[kPer];
-    auto load_step = [&](int s0) {
+    // staging: thread t -> chirp m0 + t / kTpr, samples kSpt (t % kTpr) .. + kSpt - 1 of the chunk
+    const int srow = threadIdx.x / kTpr, spart = threadIdx.x % kTpr;
+    const bool row_ok = m0 + srow < mc;
+    const float4* ysrc = reinterpret_cast<const float4*>(y + ((size_t)q * mc + (row_ok ? m0 + srow : 0)) * ms);
+    float4 st[kSpt / 2];
+    auto load_chunk = [&](int s0) {
 #pragma unroll
-        for (int i = 0; i < kPer; ++i) {
-            const int idx = threadIdx.x + i * kThreads;
-            const int row = idx >> 4, c4 = idx & 15;
-            const int m = m0 + row, s = s0 + 2 * c4;
-            stage[i] = (m < mc && s < ms) ? yq4[((size_t)m * ms + s) >> 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int i = 0; i < kSpt / 2; ++i) {
+            const int s = s0 + kSpt * spart + 2 * i;
+            st[i] = (row_ok && s < ms) ? ysrc[s >> 1] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
     };
-    auto store_step = [&](int buf) {
+    auto store_chunk = [&](int b) {
+        u32x4* dst = reinterpret_cast<u32x4*>(ys[b] + srow * kRzRowWords + kSpt * spart);
 #pragma unroll
-        for (int i = 0; i < kPer; ++i) {
-            const int idx = threadIdx.x + i * kThreads;
-            ytile[buf][idx >> 4][idx & 15] = stage[i];
-        }
+        for (int i = 0; i < kSpt / 4; ++i)
+            dst[i] = u32x4{bf16_pair(st[2 * i].x, st[2 * i].y), bf16_pair(st[2 * i].z, st[2 * i].w),
+                           bf16_pair(st[2 * i + 1].x, st[2 * i + 1].y), bf16_pair(st[2 * i + 1].z, st[2 * i + 1].w)};
     };
-    load_step(0);
-    store_step(0);
+
+    load_chunk(0);
+    store_chunk(0);
     __syncthreads();
     int buf = 0;
-    for (int s0 = 0; s0 < ms; s0 += 32) {
-        const bool more = s0 + 32 < ms;
-        if (more) load_step(s0 + 32);
-        const int sb = s0 + seg * kRun;
-        const bool live = sb < ms;   // Ms is a power of two >= 8: a run is all in or all out
-        float2 a[kRun];
-        atom_run(fr, (uint32_t)sb, ratio, a);
-        if (!live) {
+    for (int s0 = 0; s0 < ms; s0 += chunk) {
+        const bool more = s0 + chunk < ms;
+        if (more) load_chunk(s0 + chunk);
+        for (int k = 0; k < ksteps; ++k) {
+            u32x4 b[CT];
 #pragma unroll
-            for (int e = 0; e < kRun; ++e) a[e] = make_float2(0.f, 0.f);
-        }
+            for (int ct = 0; ct < CT; ++ct)
+                b[ct] = *reinterpret_cast<const u32x4*>(ys[buf] + (16 * ct + r) * kRzRowWords + 16 * k + 4 * seg);
 #pragma unroll
-        for (int t = 0; t < kNT; ++t) {
-            float2 b[kRun];
-            const float4* row = ytile[buf][t * 16 + r] + seg * (kRun / 2);
+            for (int lt = 0; lt < LT; ++lt) {
+                u32x4 are, aim;
 #pragma unroll
-            for (int i = 0; i < kRun / 2; ++i) {
-                const float4 v = row[i];
-                b[2 * i] = make_float2(v.x, v.y);
-                b[2 * i + 1] = make_float2(v.z, v.w);
+                for (int e = 0; e < 4; ++e) {
+                    are[e] = bf16_pair(at[lt][e].x, -at[lt][e].y);
+                    aim[e] = bf16_pair(at[lt][e].y, at[lt][e].x);
+                    at[lt][e] = cmul(at[lt][e], rho[lt]);
+                }
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) {
+                    cre[lt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(are), as_bf16x8(b[ct]),
+                                                                          cre[lt][ct], 0, 0, 0);
+                    cim[lt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(aim), as_bf16x8(b[ct]),
+                                                                          cim[lt][ct], 0, 0, 0);
+                }
             }
-            mfma_complex<BF16>(a, b, cre[t], cim[t]);
         }
-        if (more) store_step(buf ^ 1);
+        if (more) store_chunk(buf ^ 1);
         __syncthreads();
         buf ^= 1;
     }
+    // output element (location 4 seg + e, chirp r) of each tile
 #pragma unroll
-    for (int t = 0; t < kNT; ++t) {
-        const int m = m0 + t * 16 + r;
+    for (int lt = 0; lt < LT; ++lt) {
+        uint64_t f0e[4], hse[4];
+        if constexpr (CHIRP) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int loc = loc0 + 4 * seg + e;
-            if (loc < gp.nloc && m < mc) gws[((size_t)q * gp.nloc + loc) * mc + m] = make_float2(cre[t][e], cim[t][e]);
+            for (int e = 0; e < 4; ++e) {   // rates of location 4 seg + e, computed by lane 4 seg + e
+                const int src = 4 * seg + e;
+                f0e[e] = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(f0l[lt] >> 32), src, 64) << 32) |
+                         (uint32_t)__shfl((int)(uint32_t)f0l[lt], src, 64);
+                hse[e] = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(hsl[lt] >> 32), src, 64) << 32) |
+                         (uint32_t)__shfl((int)(uint32_t)hsl[lt], src, 64);
+            }
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            const int m = m0 + 16 * ct + r;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int loc = loc0 + 16 * lt + 4 * seg + e;
+                if (loc < gp.nloc && m < mc) {
+                    if constexpr (CHIRP) {
+                        const int mcp = mc < 16 ? 16 : mc;
+                        const uint32_t ph = fixed_mul_hi(f0e[e], (uint32_t)m) +
+                                            fixed_mul_hi(hse[e], (uint32_t)(m * m));
+                        const float2 hv = cmul(make_float2(cre[lt][ct][e], cim[lt][ct][e]), expm_hw(ph));
+                        static_cast<uint32_t*>(out)[((size_t)q * gp.nloc + loc) * mcp + m] = bf16_pair(hv.x, hv.y);
+                    } else {
+                        static_cast<float2*>(out)[((size_t)q * gp.nloc + loc) * mc + m] =
+                            make_float2(cre[lt][ct][e], cim[lt][ct][e]);
+                    }
+                }
+            }
         }
     }
 }
@@ -327,37 +440,296 @@ __global__ __launch_bounds__(kThreads) void direct_doppler_zoom(Geom g, GridP gp
     }
 }
 
+// Doppler zoom with BF16 operands through chirp tables.  With
+// f_d = f0 + ivx fx + ivy fy and 2 ivx m = ivx^2 + m^2 - (ivx - m)^2 (likewise
+// for ivy), the correlation of one receiver is
+//   c[ivx][ivy] = exp(-j pi (fx ivx^2 + fy ivy^2)) sum_m h[m] Tx[ivx - m] Ty[ivy - m],
+//   h[m] = G[m] exp(-j 2 pi (f0 m + (fx + fy) m^2 / 2)),
+//   Tx[k] = exp(j pi fx k^2),  Ty[k] = exp(j pi fy k^2);
+// the leading factor has modulus one and drops out of |c|^2.  The left operand
+// (rows ivx, contraction m) is the Toeplitz matrix Tx[ivx - m], read from a
+// table of Mc + 15 values per 16-row tile span; the right one is h[m] Ty[ivy - m],
+// formed per element by two BF16 dot products (its real and imaginary parts).
+// A (location, receiver) pair thus generates O(Mc + Nvx + Nvy) values instead
+// of O(Mc (Nvx + Nvy)).
+//
+// One wave per location, receivers in turn.  For receiver q the wave writes,
+// into its own LDS region, the chirp tables in both left-operand forms
+// (tx1 = (re, -im), tx2 = (im, re) of Tx; ty1, ty2 likewise of Ty) and h as
+// BF16 pairs:
+//   tx[n], n in [0, ex):  Tx[k] with k = nvx_pad - 1 - n (so a lane's four
+//                         contraction slots read four consecutive entries)
+//   ty[n], n in [0, ey):  Ty[k] with k = nvy_pad - 1 - n
+//   h[m],  m in [0, mcp): zero for m >= Mc
+// then walks the 16 x 16 tiles of the velocity slab column tile by column
+// tile: the right-operand fragments h[m] Ty[ivy - m] of a column tile are
+// formed once, in registers, for all its row tiles.  |c_q|^2 accumulates per
+// tile in registers across receivers (at most MAXT tiles, MAXS 16-chirp
+// steps).  h of the next receiver is loaded while the current one is in work.
+// Phases are 64-bit fixed point in cycles; the table values come from the
+// hardware sine and cosine (absolute error near 1e-6, far below the BF16
+// rounding of the operands they feed).
+template <int MAXT, int MAXS, bool STREAM>
+__global__ __launch_bounds__(kThreads) void direct_doppler_zoom_chirp(Geom g, GridP gp, ToepPlan tp,
+                                                                     const uint32_t* __restrict__ hws,
+                                                                     float* __restrict__ dec,
+                                                                     gh_peak* __restrict__ block,
+                                                                     const int64_t* __restrict__ excl, int nexcl) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t toep_lds[];
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15;
+    const int seg = lane >> 4;
+    const int w = threadIdx.x >> 6;
+    const int loc = blockIdx.x * (blockDim.x >> 6) + w;
+    if (loc >= gp.nloc) return;   // wave-uniform; the kernel has no workgroup barrier
+    uint32_t* tx1 = toep_lds + (size_t)w * tp.words;
+    uint32_t* tx2 = tx1 + tp.ex;
+    uint32_t* ty1 = tx2 + tp.ex;
+    uint32_t* ty2 = ty1 + tp.ey;
+    uint32_t* hh = ty2 + tp.ey;
+    const int ix = loc / gp.n[1], iy = loc - ix * gp.n[1];
+    const int nvx = gp.n[2], nvy = gp.n[3], nv = gp.nv, mc = g.mc;
+    const int nvxp = (nvx + 15) & ~15, nvyp = (nvy + 15) & ~15;
+    const int tiles_x = nvxp >> 4, ntiles = tiles_x * (nvyp >> 4);
+    const int steps = tp.mcp >> 4;
+
+    constexpr int kHw = (16 * MAXS + 63) / 64;   // h words per lane held ahead (cached path)
+    uint32_t hpre[kHw];
+    auto load_h = [&](int q) {
+        const uint32_t* hq = hws + ((size_t)q * gp.nloc + loc) * tp.mcp;
+#pragma unroll
+        for (int u = 0; u < kHw; ++u) {
+            const int m = lane + 64 * u;
+            hpre[u] = m < mc ? hq[m] : 0u;
+        }
+    };
+    if (!STREAM) load_h(0);
+
+    // receiver `lane`: fx / 2 and fy / 2 in 64-bit fixed point
+    uint64_t hxl = 0, hyl = 0;
+    if (lane < g.k) {
+        double rr, wx, wy;
+        bistatic(g, lane, gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], rr, wx, wy);
+        hxl = cycles_to_fixed64(0.5 * g.fd_per_mps * wx * gp.step[2]);
+        hyl = cycles_to_fixed64(0.5 * g.fd_per_mps * wy * gp.step[3]);
+    }
+    auto bcast64 = [](uint64_t v, int src) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+        return ((uint64_t)hi << 32) | lo;
+    };
+
+    f32x4 dsum[MAXT];
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) dsum[t] = zero4();
+
+    for (int q = 0; q < g.k; ++q) {
+        // every lane has finished reading receiver q - 1's tables (in-order LDS per wave)
+        __builtin_amdgcn_wave_barrier();
+        if constexpr (STREAM) {
+            const uint32_t* hq = hws + ((size_t)q * gp.nloc + loc) * tp.mcp;
+            for (int m = lane; m < tp.mcp; m += 64) hh[m] = m < mc ? hq[m] : 0u;
+        } else {
+#pragma unroll
+            for (int u = 0; u < kHw; ++u) {
+                const int m = lane + 64 * u;
+                if (m < tp.mcp) hh[m] = hpre[u];
+            }
+            if (q + 1 < g.k) load_h(q + 1);
+        }
+        const uint64_t hx = bcast64(hxl, q), hy = bcast64(hyl, q);
+        for (int n = lane; n < tp.ex; n += 64) {
+            const int k = nvxp - 1 - n;
+            const float2 e = expm_hw(fixed_mul_hi(hx, (uint32_t)(k * k)));   // conj(Tx[k])
+            tx1[n] = bf16_pair(e.x, e.y);
+            tx2[n] = bf16_pair(-e.y, e.x);
+        }
+        for (int n = lane; n < tp.ey; n += 64) {
+            const int k = nvyp - 1 - n;
+            const float2 e = expm_hw(fixed_mul_hi(hy, (uint32_t)(k * k)));   // conj(Ty[k])
+            ty1[n] = bf16_pair(e.x, e.y);
+            ty2[n] = bf16_pair(-e.y, e.x);
+        }
+        // the tables are private to the wave: its LDS writes only have to land before its reads
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+
+        u32x4 bc[STREAM ? 1 : MAXS];
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+            if (t < ntiles) {
+                const int ty = t / tiles_x, tx = t - ty * tiles_x;
+                if (!STREAM && tx == 0) {
+                    // column ivy = 16 ty + r; slot e of step s is chirp m = 16 s + 4 seg + e
+                    const uint32_t* pb1 = ty1 + 4 * seg - 16 * ty - r + nvyp - 1;
+                    const uint32_t* pb2 = pb1 + tp.ey;
+#pragma unroll
+                    for (int s = 0; s < MAXS; ++s) {
+                        if (s < steps) {
+                            const u32x4 hv = *reinterpret_cast<const u32x4*>(hh + 16 * s + 4 * seg);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                bc[STREAM ? 0 : s][e] = bf16_pair(dot2_bf16(hv[e], pb1[16 * s + e]),
+                                                                  dot2_bf16(hv[e], pb2[16 * s + e]));
+                        }
+                    }
+                }
+                // row ivx = 16 tx + r
+                const uint32_t* pa1 = tx1 + 4 * seg - 16 * tx - r + nvxp - 1;
+                const uint32_t* pa2 = pa1 + tp.ex;
+                f32x4 cr0 = zero4(), ci0 = zero4(), cr1 = zero4(), ci1 = zero4();
+                if constexpr (STREAM) {
+                    // Mc > 16 MAXS: the right operand formed step by step (steps is even)
+                    const uint32_t* pb1 = ty1 + 4 * seg - 16 * ty - r + nvyp - 1;
+                    const uint32_t* pb2 = pb1 + tp.ey;
+                    auto step = [&](int o, f32x4& cr, f32x4& ci) {
+                        const u32x4 ar = {pa1[o], pa1[o + 1], pa1[o + 2], pa1[o + 3]};
+                        const u32x4 ai = {pa2[o], pa2[o + 1], pa2[o + 2], pa2[o + 3]};
+                        const u32x4 hv = *reinterpret_cast<const u32x4*>(hh + o + 4 * seg);
+                        u32x4 bv;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            bv[e] = bf16_pair(dot2_bf16(hv[e], pb1[o + e]), dot2_bf16(hv[e], pb2[o + e]));
+                        cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ar), as_bf16x8(bv), cr, 0, 0, 0);
+                        ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ai), as_bf16x8(bv), ci, 0, 0, 0);
+                    };
+                    for (int s2 = 0; s2 < steps; s2 += 2) {
+                        step(16 * s2, cr0, ci0);
+                        step(16 * s2 + 16, cr1, ci1);
+                    }
+                } else {
+#pragma unroll
+                    for (int s = 0; s < MAXS; ++s) {
+                        if (s < steps) {
+                            const int o = 16 * s;
+                            const u32x4 ar = {pa1[o], pa1[o + 1], pa1[o + 2], pa1[o + 3]};
+                            const u32x4 ai = {pa2[o], pa2[o + 1], pa2[o + 2], pa2[o + 3]};
+                            f32x4& cr = (s & 1) ? cr1 : cr0;
+                            f32x4& ci = (s & 1) ? ci1 : ci0;
+                            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ar), as_bf16x8(bc[s]), cr, 0, 0, 0);
+                            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ai), as_bf16x8(bc[s]), ci, 0, 0, 0);
+                        }
+                    }
+                }
+                cr0 += cr1;
+                ci0 += ci1;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) dsum[t][e] = fmaf(cr0[e], cr0[e], fmaf(ci0[e], ci0[e], dsum[t][e]));
+            }
+        }
+    }
+
+    const int64_t base = (int64_t)loc * nv;
+    float best_v = -INFINITY;
+    int best_i = 0x7fffffff;
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+        if (t < ntiles) {
+            const int ty = t / tiles_x, tx = t - ty * tiles_x;
+            const int ivy = ty * 16 + r;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int ivx = tx * 16 + 4 * seg + e;
+                if (ivx < nvx && ivy < nvy) {
+                    const int v = ivx * nvy + ivy;
+                    if (dec) dec[base + v] = dsum[t][e];
+                    bool skip = false;
+                    for (int i = 0; i < nexcl; ++i) skip |= (excl[i] == base + v);
+                    if (!skip) peak_merge(best_v, best_i, dsum[t][e], v);
+                }
+            }
+        }
+    }
+    wave_peak(best_v, best_i);
+    if (lane == 0) {
+        gh_peak p;
+        p.value = best_v;
+        p.reserved = 0;
+        p.index = base + (best_i == 0x7fffffff ? 0 : best_i);
+        block[loc] = p;
+    }
+}
+
+// Launch shape of the chirp-table Doppler zoom: the register bounds it was
+// instantiated for (MAXT 4 or 16 tiles, MAXS 8 steps, i.e. Mc <= 128), and
+// waves per workgroup from its LDS (one table set per wave); 0 when the
+// slab or the chirp count exceeds those bounds (then the generating Doppler
+// zoom runs).
+struct ChirpShape {
+    int maxt, waves;
+    bool stream;
+};
+
+ChirpShape chirp_shape(const Geom& g, const GridP& gp) {
+    const ToepPlan tp = toep_plan(g.mc, gp.n[2], gp.n[3]);
+    const int ntiles = ((gp.n[2] + 15) >> 4) * ((gp.n[3] + 15) >> 4);
+    if (ntiles > 16) return {0, 0, false};
+    const size_t per_wave = (size_t)tp.words * 4;
+    int w = kWaves;
+    while (w > 1 && w * per_wave > 65536) w >>= 1;
+    if (w * per_wave > 65536) return {0, 0, false};
+    return {ntiles <= 4 ? 4 : 16, w, tp.mcp > 128};
+}
+
 }  // namespace
 
 size_t direct_ws_bytes(const Geom& g, const GridP& gp, int /*gemm*/) {
     return (size_t)g.k * gp.nloc * g.mc * sizeof(float2);
 }
 
-hipError_t launch_direct_range(const Geom& g, const GridP& gp, const float2* y, int gemm, float2* G, hipStream_t st) {
-    const dim3 g1((gp.nloc + 16 * kWaves - 1) / (16 * kWaves), (g.mc + 16 * kNT - 1) / (16 * kNT), g.k);
-    if (gemm == GH_GEMM_BF16)
-        hipLaunchKernelGGL(direct_range_zoom_bf16, g1, dim3(kThreads), 0, st, g, gp, y, G);
+// BF16 range zoom: 16 CT chirps per workgroup (CT = 4 unless Mc < 64), 64 locations.
+template <bool CHIRP>
+hipError_t launch_range_bf16(const Geom& g, const GridP& gp, const float2* y, void* out, hipStream_t st) {
+    const int ct = g.mc >= 64 ? 4 : (g.mc >= 32 ? 2 : 1);
+    const dim3 grid((gp.nloc + 16 * kWaves - 1) / (16 * kWaves), (g.mc + 16 * ct - 1) / (16 * ct), g.k);
+    if (ct == 4)
+        hipLaunchKernelGGL((direct_range_zoom_bf16<1, 4, CHIRP>), grid, dim3(kThreads), 0, st, g, gp, y, out);
+    else if (ct == 2)
+        hipLaunchKernelGGL((direct_range_zoom_bf16<1, 2, CHIRP>), grid, dim3(kThreads), 0, st, g, gp, y, out);
     else
-        hipLaunchKernelGGL(direct_range_zoom<false>, g1, dim3(kThreads), 0, st, g, gp, y, G);
+        hipLaunchKernelGGL((direct_range_zoom_bf16<1, 1, CHIRP>), grid, dim3(kThreads), 0, st, g, gp, y, out);
     return hipGetLastError();
 }
 
+hipError_t launch_direct_range(const Geom& g, const GridP& gp, const float2* y, int gemm, float2* G, hipStream_t st) {
+    if (gemm == GH_GEMM_BF16) return launch_range_bf16<false>(g, gp, y, G, st);
+    const dim3 g1((gp.nloc + 16 * kWaves - 1) / (16 * kWaves), (g.mc + 16 * kNT - 1) / (16 * kNT), g.k);
+    hipLaunchKernelGGL(direct_range_zoom<false>, g1, dim3(kThreads), 0, st, g, gp, y, G);
+    return hipGetLastError();
+}
+
+// BF16: the chirp-table Doppler zoom on h from the range zoom when its tables
+// fit in LDS, else the generating Doppler zoom on G.  The workspace holds G
+// (complex64) or h (BF16 pairs, at most as many bytes).
 hipError_t launch_direct(const Geom& g, const GridP& gp, const float2* y, int gemm, void* ws, float* dec,
                          gh_peak* block, const int64_t* excl, int nexcl, hipStream_t st) {
     float2* gws = static_cast<float2*>(ws);
-    const dim3 g1((gp.nloc + 16 * kWaves - 1) / (16 * kWaves), (g.mc + 16 * kNT - 1) / (16 * kNT), g.k);
-    const dim3 g2((gp.nloc + kWaves - 1) / kWaves);
+    hipError_t e;
     if (gemm == GH_GEMM_BF16) {
-        hipLaunchKernelGGL(direct_range_zoom_bf16, g1, dim3(kThreads), 0, st, g, gp, y, gws);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(direct_doppler_zoom<true>, g2, dim3(kThreads), 0, st, g, gp, gws, dec, block, excl, nexcl);
+        const ChirpShape cs = chirp_shape(g, gp);
+        if (cs.waves > 0) {
+            if ((e = launch_range_bf16<true>(g, gp, y, ws, st)) != hipSuccess) return e;
+            const ToepPlan tp = toep_plan(g.mc, gp.n[2], gp.n[3]);
+            const size_t lds = (size_t)cs.waves * tp.words * 4;
+            const dim3 grid((gp.nloc + cs.waves - 1) / cs.waves), blk(64 * cs.waves);
+            const uint32_t* h = static_cast<const uint32_t*>(ws);
+#define GH_CHIRP_LAUNCH(T, S) \
+    hipLaunchKernelGGL((direct_doppler_zoom_chirp<T, 8, S>), grid, blk, lds, st, g, gp, tp, h, dec, block, excl, nexcl)
+            if (cs.maxt == 4) {
+                if (cs.stream) GH_CHIRP_LAUNCH(4, true); else GH_CHIRP_LAUNCH(4, false);
+            } else {
+                if (cs.stream) GH_CHIRP_LAUNCH(16, true); else GH_CHIRP_LAUNCH(16, false);
+            }
+#undef GH_CHIRP_LAUNCH
+        } else {
+            if ((e = launch_range_bf16<false>(g, gp, y, ws, st)) != hipSuccess) return e;
+            hipLaunchKernelGGL(direct_doppler_zoom<true>, dim3((gp.nloc + kWaves - 1) / kWaves), dim3(kThreads), 0,
+                               st, g, gp, gws, dec, block, excl, nexcl);
+        }
     } else {
-        hipLaunchKernelGGL(direct_range_zoom<false>, g1, dim3(kThreads), 0, st, g, gp, y, gws);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(direct_doppler_zoom<false>, g2, dim3(kThreads), 0, st, g, gp, gws, dec, block, excl,
-                           nexcl);
+        if ((e = launch_direct_range(g, gp, y, gemm, gws, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(direct_doppler_zoom<false>, dim3((gp.nloc + kWaves - 1) / kWaves), dim3(kThreads), 0, st,
+                           g, gp, gws, dec, block, excl, nexcl);
     }
     return hipGetLastError();
 }
