@@ -60,6 +60,7 @@ sys.path.insert(0, ROOT)
 CFG = 2
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0   # dense matrix-core BF16
 FLOP_PER_POINT_RX = {"bilinear": 12, "bicubic": 44}   # algorithmic, per grid point and receiver
 PRECISION_CFG = 3
 CUS = 256                 # MI355X compute units
@@ -71,6 +72,13 @@ INTERNAL_HEADER = os.path.join(ROOT, "paper_2307_16550_amd", "csrc", "gh_interna
 DEVICE_PART_END = "// ---- batches of frames"   # gh_internal.h from here on declares host launchers only
 BATCH_REPLAYS = 10
 EAGER_ROW_STEPS = 20
+
+
+def direct_flop(radar, n):
+    """Algorithmic FLOPs of the direct decision: both complex contractions per
+    receiver, range zoom K Nloc Ms Mc and Doppler zoom K Nloc Nv Mc multiply-adds."""
+    nloc, nv = n[0] * n[1], n[2] * n[3]
+    return 8.0 * radar.k * radar.mc * nloc * (radar.ms + nv)
 
 
 def recorded_traffic(key="traffic_bytes_per_launch"):
@@ -523,7 +531,8 @@ def main():
         s3 = sc.make_scene(PRECISION_CFG, 0)
         r3 = gh.Radar.from_scene(s3)
         g3 = gh.grid_of(s3.grid)
-        z3 = gh.rd_maps(r3, torch.from_numpy(s3.y).to(dev))
+        y3 = torch.from_numpy(s3.y).to(dev)
+        z3 = gh.rd_maps(r3, y3)
         dec3 = torch.empty(tuple(s3.grid.n), dtype=torch.float32, device=dev)
         blk3 = gh.peaks_tensor(s3.grid.n[0] * s3.grid.n[1], dev)
         for _ in range(3):
@@ -536,7 +545,20 @@ def main():
         torch.cuda.synchronize()
         t3 = p0.elapsed_time(p1) * 1e-3 / 10
         bytes3 = 4 * s3.grid.size + z3.numel() * 8 + 16 * blk3.shape[0]
-        del dec3, z3
+        del z3
+        # the BF16 direct decision on the same whole grid (volume written)
+        ws3 = torch.empty(gh.direct_workspace_bytes(r3, g3, gh.GEMM_BF16), dtype=torch.uint8, device=dev)
+        for _ in range(2):
+            gh.direct_decision(r3, g3, y3, gemm=gh.GEMM_BF16, ws=ws3, dec=dec3, block=blk3, want_argmax=False)
+        q0, q1 = ev(), ev()
+        q0.record(stream)
+        for _ in range(5):
+            gh.direct_decision(r3, g3, y3, gemm=gh.GEMM_BF16, ws=ws3, dec=dec3, block=blk3, want_argmax=False)
+        q1.record(stream)
+        torch.cuda.synchronize()
+        t_dir3 = q0.elapsed_time(q1) * 1e-3 / 5
+        flop_dir3 = direct_flop(r3, s3.grid.n)
+        del dec3, ws3, y3
 
         # the direct decision with BF16 matrix-core operands, timed on its own (not part of the step)
         ws_b = torch.empty(gh.direct_workspace_bytes(radar, dgrid, gh.GEMM_BF16), dtype=torch.uint8, device=dev)
@@ -557,6 +579,8 @@ def main():
             "copy_gbs": copy_gbs,
             "t_gh_sub": t_gh_sub,
             "t_dir_bf16": t_dir_bf16,
+            "t_dir_bf16_precision": t_dir3,
+            "flop_dir_bf16_precision": flop_dir3,
             "err_bf16": err_bf16,
             "t_sel": t_sel,
             "precision": {"t": t3, "bytes": bytes3, "points": s3.grid.size, "k": r3.k},
@@ -618,6 +642,17 @@ def main():
         line.update({
             "direct_bf16_points_per_s": n_dir / x["t_dir_bf16"],
             "direct_bf16_max_rel_diff_vs_f32": x["err_bf16"],
+            # algorithmic matrix-core work (8 flops per complex multiply-add of both zooms)
+            # against the dense BF16 peak, on the paper-scale subgrid and the precision grid
+            "direct_bf16_mfma": {
+                "unit": "TFLOP/s", "peak": BF16_PEAK_TFLOPS,
+                "subgrid": {"us": x["t_dir_bf16"] * 1e6, "flop": direct_flop(radar, dgrid_s.n),
+                            "achieved": direct_flop(radar, dgrid_s.n) / x["t_dir_bf16"] / 1e12,
+                            "frac": direct_flop(radar, dgrid_s.n) / x["t_dir_bf16"] / 1e12 / BF16_PEAK_TFLOPS},
+                "precision_grid": {"us": x["t_dir_bf16_precision"] * 1e6, "flop": x["flop_dir_bf16_precision"],
+                                   "achieved": x["flop_dir_bf16_precision"] / x["t_dir_bf16_precision"] / 1e12,
+                                   "frac": x["flop_dir_bf16_precision"] / x["t_dir_bf16_precision"] / 1e12
+                                   / BF16_PEAK_TFLOPS}},
             "speedup_gh_over_direct_same_subgrid": t_dir / x["t_gh_sub"],
             "ms_per_step_p10_p50_p90": x["ms_per_step_p10_p50_p90"],
             "ms_per_step_one_stream": x["ms_per_step_one_stream"],
