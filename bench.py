@@ -373,15 +373,15 @@ def main():
         gh.decision(radar, grid, fmaps, interp, dec=dec, block=block, want_argmax=False)
         if record:
             e[2].record(stream)
-        gh.argmax(block, arg)
+        # the grid-hopping argmax is Block-OMP's first selection: one launch for both
+        bomp.reset()
+        bomp.seed(block, selected=arg)
         if record:
             e[3].record(stream)
         gh.direct_decision(radar, dgrid, y, ws=ws, dec=ddec, block=dblock, want_argmax=False)
         if record:
             e[4].record(stream)
         gh.argmax(dblock, darg)
-        bomp.reset()
-        bomp.seed(arg)
         bomp.fit()
         for _ in range(BOMP_ITERS - 1):
             bomp.step()
@@ -419,9 +419,8 @@ def main():
             gh.argmax(dblock, darg)
         gh.rd_maps(radar, y, fmaps)
         gh.decision(radar, grid, fmaps, interp, dec=dec, block=block, want_argmax=False)
-        gh.argmax(block, arg)
         bomp.reset()
-        bomp.seed(arg)
+        bomp.seed(block, selected=arg)
         bomp.fit()
         for _ in range(BOMP_ITERS - 2):
             bomp.step()

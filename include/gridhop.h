@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define GH_ABI_VERSION 3
+#define GH_ABI_VERSION 4
 #define GH_MAX_RX 16
 #define GH_MAX_SUPPORT 32
 #define GH_REFINE_NOALLOC_MAX_CELLS 1024              /* cells per gh_refine_noalloc call */
@@ -225,14 +225,16 @@ int gh_bomp_select(const gh_radar *radar, const gh_grid *grid, const void *d_y, 
  * that a caller who needs both that decision (its volume, say) and Block-OMP
  * computes the frame's maps and the first sweep once.  Preconditions (the
  * caller's): the run's d_maps holds gh_rd_maps of d_y (complex64), the buffer
- * later passed to gh_bomp_select / gh_bomp_step, and d_argmax holds the
- * gh_decision (or gh_argmax) maximum over the same grid with the same interp,
- * computed from those maps.  Writes d_support[0] = d_argmax->index and, when
- * d_selected is non-NULL, *d_selected = *d_argmax, and readies d_ws (of
- * gh_bomp_workspace_bytes(radar, grid, 0, any gemm_dtype) bytes) for the later
- * selections.  The run then continues with gh_bomp_fit(n_selected = 1).
- * max_support and interp as in gh_bomp_step. */
-int gh_bomp_seed(const gh_radar *radar, const gh_grid *grid, int32_t interp, const gh_peak *d_argmax,
+ * later passed to gh_bomp_select / gh_bomp_step, and d_block holds the
+ * per-location maxima (gh_peak [Nx*Ny]) of gh_decision over the same grid with
+ * the same interp, computed from those maps.  Takes their maximum (the
+ * argmax of eqs. (5)-(6), ties to the lowest index, as gh_argmax), writes
+ * its index to d_support[0] and, when d_selected is non-NULL, the maximum
+ * itself to *d_selected, and readies d_ws (of gh_bomp_workspace_bytes(radar,
+ * grid, 0, any gemm_dtype) bytes) for the later selections; one launch.  The
+ * run then continues with gh_bomp_fit(n_selected = 1).  max_support and
+ * interp as in gh_bomp_step. */
+int gh_bomp_seed(const gh_radar *radar, const gh_grid *grid, int32_t interp, const gh_peak *d_block,
                  int64_t *d_support, int32_t max_support, gh_peak *d_selected, void *d_ws, size_t ws_bytes,
                  void *stream);
 

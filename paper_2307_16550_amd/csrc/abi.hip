@@ -424,20 +424,23 @@ int gh_bomp_select(const gh_radar* radar, const gh_grid* grid, const void* d_y, 
     return ok();
 }
 
-int gh_bomp_seed(const gh_radar* radar, const gh_grid* grid, int32_t interp, const gh_peak* d_argmax,
+int gh_bomp_seed(const gh_radar* radar, const gh_grid* grid, int32_t interp, const gh_peak* d_block,
                  int64_t* d_support, int32_t max_support, gh_peak* d_selected, void* d_ws, size_t ws_bytes,
                  void* stream) {
     gh::Geom g;
     gh::GridP gp;
     int rc = bomp_common(radar, grid, 0, interp, GH_GEMM_F32, max_support, g, gp);
     if (rc) return rc;
-    if (!d_argmax || !d_support || !d_ws) return fail(GH_EINVAL, "NULL device pointer");
-    if ((rc = check_aligned({d_argmax, d_support, d_selected, d_ws}))) return rc;
+    if (!d_block || !d_support || !d_ws) return fail(GH_EINVAL, "NULL device pointer");
+    if ((rc = check_aligned({d_block, d_support, d_selected, d_ws}))) return rc;
     const size_t need = gh_bomp_workspace_bytes(radar, grid, 0, GH_GEMM_F32);
     if (ws_bytes < need) return fail(GH_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if ((rc = check_device())) return rc;
     char* split_ws = bomp_split_ws(g, gp, 0, GH_GEMM_F32, (char*)d_ws);
-    const hipError_t e = gh::launch_bomp_seed(d_argmax, d_support, d_selected, (unsigned*)split_ws, (hipStream_t)stream);
+    // the grid maximum straight into the support and the selected peak, zeroing
+    // the counter of the later selections' split maximum
+    const hipError_t e = gh::launch_peak_final(d_block, gp.nloc, d_selected, d_support, (hipStream_t)stream,
+                                               (unsigned*)split_ws);
     if (e != hipSuccess) return hip_fail(e, "gh_bomp_seed launch");
     return ok();
 }

@@ -308,23 +308,6 @@ __global__ __launch_bounds__(kThreads) void bomp_resid_maps_kernel(Geom g, ResRo
 
 }  // namespace
 
-// The first Block-OMP selection taken from a grid-hopping maximum the caller
-// computed on the frame itself: support[0] and the selected peak from it, and
-// the selection counter of the split grid maximum zeroed for the later ones.
-__global__ void bomp_seed_kernel(const gh_peak* __restrict__ argmax, int64_t* __restrict__ support,
-                                 gh_peak* __restrict__ selected, unsigned* __restrict__ counter) {
-    const gh_peak p = *argmax;
-    support[0] = p.index;
-    if (selected) *selected = p;
-    *counter = 0u;
-}
-
-hipError_t launch_bomp_seed(const gh_peak* argmax, int64_t* support, gh_peak* selected, unsigned* counter,
-                            hipStream_t st) {
-    hipLaunchKernelGGL(bomp_seed_kernel, dim3(1), dim3(1), 0, st, argmax, support, selected, counter);
-    return hipGetLastError();
-}
-
 bool bomp_resid_maps_ok(const Geom& g, int nsel) {
     return nsel >= 1 && nsel <= kMaxSupport && (long)nsel * g.nd <= kResTable && g.nr % kResRows == 0;
 }

@@ -393,8 +393,6 @@ hipError_t launch_bomp_fit(const Geom& g, const GridP& gp, const float2* y, floa
 // written; the other rows of `out` keep their contents.
 bool bomp_resid_maps_ok(const Geom& g, int nsel);
 // support[0] (and *selected, if given) from *argmax; *counter zeroed.
-hipError_t launch_bomp_seed(const gh_peak* argmax, int64_t* support, gh_peak* selected, unsigned* counter,
-                            hipStream_t st);
 hipError_t launch_bomp_resid_maps(const Geom& g, const GridP& gp, const float2* maps_y, const float2* atom_vec,
                                   int nsel, float2* out, hipStream_t st);
 

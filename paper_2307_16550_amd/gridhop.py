@@ -333,17 +333,20 @@ class BompState:
                                   _ptr(self.ws), self.ws.numel(), _stream(stream)))
         self._selected_pending = True
 
-    def seed(self, argmax, stream=None):
-        """The first selection from a grid-hopping maximum already computed on the frame
-        (gh_bomp_seed): self.maps must hold rd_maps of y and `argmax` the decision's
-        maximum over the same grid with the same interp.  fit() completes the iteration."""
+    def seed(self, block, selected=None, stream=None):
+        """The first selection from a grid-hopping decision already made on the frame
+        (gh_bomp_seed): self.maps must hold rd_maps of y and `block` that decision's
+        per-location maxima over the same grid with the same interp.  The selected
+        maximum (the decision's argmax) goes to `selected` (gh_peak [1]) when given,
+        else to self.selected.  fit() completes the iteration."""
         if self.use_direct:
             raise ValueError("seed() applies to grid-hopping runs")
         if self._selected_pending:
             raise RuntimeError("seed() called twice without fit()")
         lib = load()
+        out = self.selected if selected is None else selected
         _check(lib.gh_bomp_seed(ctypes.byref(self.radar.c_struct), ctypes.byref(self.grid), self.interp,
-                                _ptr(argmax), _ptr(self.support), self.max_support, _ptr(self.selected),
+                                _ptr(block), _ptr(self.support), self.max_support, _ptr(out),
                                 _ptr(self.ws), self.ws.numel(), _stream(stream)))
         self.n = 0
         self._selected_pending = True

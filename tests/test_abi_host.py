@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.gh_abi_version() == 3
+    assert lib.gh_abi_version() == 4
 
 
 def radar(**kw):
@@ -151,7 +151,7 @@ def test_bomp_seed_argument_checks(lib):
     ws = lib.gh_bomp_workspace_bytes(ctypes.byref(r.c_struct), ctypes.byref(GRID), 0, 0)
     args = [ctypes.byref(r.c_struct), ctypes.byref(GRID)]
     assert lib.gh_bomp_seed(*args, 0, FAKE, FAKE, 3, None, FAKE, ws - 1, None) == gh.GH_EWORKSPACE
-    assert lib.gh_bomp_seed(*args, 0, None, FAKE, 3, None, FAKE, ws, None) == gh.GH_EINVAL        # no argmax
+    assert lib.gh_bomp_seed(*args, 0, None, FAKE, 3, None, FAKE, ws, None) == gh.GH_EINVAL        # no block maxima
     assert lib.gh_bomp_seed(*args, 0, FAKE, FAKE, 33, None, FAKE, ws, None) == gh.GH_EINVAL       # max_support
     assert lib.gh_bomp_seed(*args, 5, FAKE, FAKE, 3, None, FAKE, ws, None) == gh.GH_EINVAL        # interp
     assert lib.gh_bomp_seed(*args, 0, FAKE, ctypes.c_void_p(0x1004), 3, None, FAKE, ws, None) == gh.GH_EINVAL

@@ -386,9 +386,10 @@ def test_bomp_many_atoms_closed_form_matches_fft():
 @pytest.mark.parametrize("interp", [gh.BILINEAR, gh.BICUBIC])
 def test_bomp_seeded_from_the_decision(interp):
     """gh_bomp_seed: the grid-hopping decision on the frame's own maps (volume
-    written) and its argmax stand in for Block-OMP's first selection; the run
-    then gives exactly the support, coefficients and residual of three
-    gh_bomp_step calls, on the paper-scale frame."""
+    written) and the maximum of its block maxima stand in for Block-OMP's first
+    selection; the seed's selected peak is gh_argmax's, and the run then gives
+    exactly the support, coefficients and residual of three gh_bomp_step calls,
+    on the paper-scale frame."""
     say(f"bomp seeded cfg=2 interp={interp}")
     s, r, gr = scene_and_radar(2, 0)
     grid = gh.grid_of(s.grid)
@@ -399,7 +400,9 @@ def test_bomp_seeded_from_the_decision(interp):
     b = gh.BompState(gr, grid, y, max_support=3, interp=interp)
     gh.rd_maps(gr, y, b.maps)
     dec, block, arg = gh.decision(gr, grid, b.maps, interp)
-    b.seed(arg)
+    sel = gh.peaks_tensor(1, y.device)
+    b.seed(block, selected=sel)
+    assert torch.equal(sel, arg)
     b.fit()
     for _ in range(2):
         b.step()
