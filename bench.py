@@ -299,7 +299,8 @@ def batch_workload(gh, sc, torch, stream):
             "frames_per_s": info["n_frames"] / ms * 1e3, "points_per_s": info["points"] / ms * 1e3,
             "replays": BATCH_REPLAYS, "hip_graph": True,
             "launch_shape": {"workgroups": info["workgroups"], "sweep_waves": info["sweep_waves"],
-                             "column_height": info["column_height"]},
+                             "column_height": info["column_height"], "sweep_locations": info["sweep_locations"],
+                             "range_chirps": info["range_chirps"], "doppler_rows": info["doppler_rows"]},
             "autotune_trials": len(tuned["trials"])}
 
 

@@ -399,7 +399,9 @@ typedef struct {
     int32_t max_workgroups[3];  /* workgroups resident at once (occupancy x compute units) */
     int32_t sweep_waves;        /* waves per sweep workgroup: 1, 2 or 4 */
     int32_t column_height;      /* compiled vx points per lane of the sweep */
-    int32_t reserved;
+    int32_t sweep_locations;    /* consecutive locations per sweep work unit (gh_batch_tune_tiles) */
+    int32_t range_chirps;       /* chirps per range workgroup requested (0: each frame's planner) */
+    int32_t doppler_rows;       /* range rows per Doppler workgroup requested (0: each frame's planner) */
     int64_t points;             /* grid points over all frames */
     int64_t workspace_bytes;    /* bytes of the workspace the batch uses */
 } gh_batch_info;
@@ -428,6 +430,18 @@ int gh_batch_create(const gh_frame *frames, int32_t n_frames, int32_t interp, vo
  * keeps).  Any positive count is correct; launches clamp to their units. */
 int gh_batch_tune(gh_batch *batch, int32_t range_workgroups, int32_t doppler_workgroups, int32_t sweep_workgroups,
                   int32_t sweep_waves);
+
+/* Tiles of the batch's launches (the autotuner's other knobs): chirps per
+ * range-pass workgroup and range rows per Doppler-pass workgroup (0: each
+ * frame's planner; else a power of two up to 4096, clamped per frame to what
+ * a workgroup holds), and consecutive locations per sweep work unit (1..64;
+ * 0 keeps).  Re-plans every frame's work units, uploads the descriptor table
+ * on `stream` and synchronises it (not for use inside a graph capture); the
+ * range and Doppler workgroup counts go back to their resident maximum.
+ * Results do not depend on the tiles.  GH_EUNSUPPORTED if a map pass would
+ * need more than 64 KB of LDS. */
+int gh_batch_tune_tiles(gh_batch *batch, int32_t range_chirps, int32_t doppler_rows, int32_t sweep_locations,
+                        void *stream);
 
 int gh_batch_get_info(const gh_batch *batch, gh_batch_info *info);
 

@@ -160,6 +160,8 @@ struct gh_batch {
     int waves = 4;
     int wg[3] = {0, 0, 0};
     int wg_max[3] = {0, 0, 0};
+    int req_nch = 0, req_nrow = 0;   // requested map-pass tiles (0: each frame's planner)
+    int loc_tile = 1;                // consecutive locations per sweep work unit
     long long points = 0;
     size_t ws_used = 0;
     gh::FrameDesc* d_table = nullptr;
@@ -194,6 +196,42 @@ int batch_layout(const gh_frame* frames, int nf, std::vector<gh::Geom>& gs, std:
         if (rc || (rc = make_grid(&frames[f].grid, gps[f]))) return frame_fail(rc, f);
         bytes += align256((size_t)gs[f].k * gs[f].nr * gs[f].nd * 8);
     }
+    return GH_OK;
+}
+
+// Map-pass tiles and work units of every frame for the requested tiles (0:
+// the frame's planner), the sweep's units for loc_tile locations each, and
+// the largest LDS of each map pass.
+int plan_units(std::vector<gh::FrameDesc>& table, int req_nch, int req_nrow, int loc_tile, int units_out[3],
+               size_t& lds1, size_t& lds2) {
+    long long units[3] = {0, 0, 0};
+    lds1 = lds2 = 0;
+    for (size_t f = 0; f < table.size(); ++f) {
+        gh::FrameDesc& d = table[f];
+        size_t l1, l2;
+        gh::rd_maps_plan(d.g, d.nch, l1, d.nrow, d.pre_lds, l2);
+        if (req_nch > 0 || req_nrow > 0) {
+            if (req_nch > 0) d.nch = req_nch;
+            if (req_nrow > 0) d.nrow = req_nrow;
+            gh::rd_maps_shape(d.g, d.nch, d.nrow, l1, d.pre_lds, l2);
+        }
+        lds1 = l1 > lds1 ? l1 : lds1;
+        lds2 = l2 > lds2 ? l2 : lds2;
+        d.nunit[0] = d.g.k * d.g.pr * (d.g.mc / d.nch);
+        d.nunit[1] = d.g.k * (d.g.nr / d.nrow);
+        d.nunit[2] = (d.gp.nloc + loc_tile - 1) / loc_tile;
+        for (int w = 0; w < 3; ++w) {
+            d.unit0[w] = (int)units[w];
+            units[w] += d.nunit[w];
+        }
+    }
+    for (int w = 0; w < 3; ++w) {
+        if (units[w] >= (1LL << 31)) return fail(GH_EUNSUPPORTED, "batch has more than 2^31 work units");
+        units_out[w] = (int)units[w];
+    }
+    // the map passes of a batch also hold the current frame's descriptor in LDS
+    if (lds1 + sizeof(gh::FrameDesc) > 65536 || lds2 + sizeof(gh::FrameDesc) > 65536)
+        return fail(GH_EUNSUPPORTED, "map passes of this batch need more than 64 KB of LDS");
     return GH_OK;
 }
 
@@ -656,7 +694,7 @@ int gh_batch_create(const gh_frame* frames, int32_t n_frames, int32_t interp, vo
     if ((rc = check_aligned({d_ws}))) return rc;
     if (ws_bytes < need) return fail(GH_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     int nd_max = 0, chunk_max = 0;
-    long long units[3] = {0, 0, 0}, points = 0;
+    long long points = 0;
     std::vector<gh::FrameDesc> table(n_frames);
     char* maps = (char*)d_ws + align256((size_t)n_frames * sizeof(gh::FrameDesc));
     size_t lds1 = 0, lds2 = 0;
@@ -680,17 +718,6 @@ int gh_batch_create(const gh_frame* frames, int32_t n_frames, int32_t interp, vo
         d.maps = maps;
         d.dec = fr.d_decision;
         d.block = fr.d_block;
-        size_t l1, l2;
-        gh::rd_maps_plan(g, d.nch, l1, d.nrow, d.pre_lds, l2);
-        lds1 = l1 > lds1 ? l1 : lds1;
-        lds2 = l2 > lds2 ? l2 : lds2;
-        d.nunit[0] = g.k * g.pr * (g.mc / d.nch);
-        d.nunit[1] = g.k * (g.nr / d.nrow);
-        d.nunit[2] = gp.nloc;
-        for (int w = 0; w < 3; ++w) {
-            d.unit0[w] = (int)units[w];
-            units[w] += d.nunit[w];
-        }
         d.nvy = nvy;
         d.parts = parts;
         d.chunk = chunk;
@@ -699,11 +726,8 @@ int gh_batch_create(const gh_frame* frames, int32_t n_frames, int32_t interp, vo
         points += (long long)gp.nloc * gp.nv;
         maps += align256((size_t)g.k * g.nr * g.nd * 8);
     }
-    for (int w = 0; w < 3; ++w)
-        if (units[w] >= (1LL << 31)) return fail(GH_EUNSUPPORTED, "batch has more than 2^31 work units");
-    // the map passes of a batch also hold the current frame's descriptor in LDS
-    if (lds1 + sizeof(gh::FrameDesc) > 65536 || lds2 + sizeof(gh::FrameDesc) > 65536)
-        return fail(GH_EUNSUPPORTED, "map passes of this batch need more than 64 KB of LDS");
+    int nunits[3];
+    if ((rc = plan_units(table, 0, 0, 1, nunits, lds1, lds2))) return rc;
     const int wave_f4 = gh::sweep_batch_slice_f4(interp, nd_max);
     int nvx_t = 0;
     gh::sweep_batch_nvx(chunk_max, nvx_t);
@@ -716,7 +740,7 @@ int gh_batch_create(const gh_frame* frames, int32_t n_frames, int32_t interp, vo
     b->device = device;
     b->nf = n_frames;
     b->interp = interp;
-    for (int w = 0; w < 3; ++w) b->units[w] = (int)units[w];
+    for (int w = 0; w < 3; ++w) b->units[w] = nunits[w];
     b->lds1 = lds1;
     b->lds2 = lds2;
     b->nvx_t = nvx_t;
@@ -769,6 +793,42 @@ int gh_batch_tune(gh_batch* batch, int32_t range_workgroups, int32_t doppler_wor
     return ok();
 }
 
+int gh_batch_tune_tiles(gh_batch* batch, int32_t range_chirps, int32_t doppler_rows, int32_t sweep_locations,
+                        void* stream) {
+    if (!batch) return fail(GH_EINVAL, "batch is NULL");
+    auto pow2_or_zero = [](int v) { return v == 0 || (v > 0 && v <= 4096 && (v & (v - 1)) == 0); };
+    if (!pow2_or_zero(range_chirps) || !pow2_or_zero(doppler_rows))
+        return fail(GH_EINVAL, "range_chirps and doppler_rows must be 0 or powers of two up to 4096");
+    if (sweep_locations < 0 || sweep_locations > 64)
+        return fail(GH_EINVAL, "sweep_locations must be in [0, 64]");
+    int dev = -1;
+    int rc = current_device(dev);
+    if (rc) return rc;
+    if (dev != batch->device) return fail(GH_EINVAL, "batch created on device %d, current device %d", batch->device, dev);
+    std::vector<gh::FrameDesc> table = batch->table;
+    const int loc_tile = sweep_locations > 0 ? sweep_locations : batch->loc_tile;
+    int units[3];
+    size_t lds1, lds2;
+    if ((rc = plan_units(table, range_chirps, doppler_rows, loc_tile, units, lds1, lds2))) return rc;
+    const int mx0 = gh::range_batch_max_workgroups(lds1), mx1 = gh::doppler_batch_max_workgroups(lds2);
+    if (mx0 < 1 || mx1 < 1) return fail(GH_EHIP, "occupancy query of the map passes failed");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(batch->d_table, table.data(), table.size() * sizeof(gh::FrameDesc),
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "gh_batch_tune_tiles upload");
+    batch->table.swap(table);
+    for (int w = 0; w < 3; ++w) batch->units[w] = units[w];
+    batch->lds1 = lds1;
+    batch->lds2 = lds2;
+    batch->wg_max[0] = batch->wg[0] = mx0;
+    batch->wg_max[1] = batch->wg[1] = mx1;
+    batch->req_nch = range_chirps;
+    batch->req_nrow = doppler_rows;
+    batch->loc_tile = loc_tile;
+    return ok();
+}
+
 int gh_batch_get_info(const gh_batch* batch, gh_batch_info* info) {
     if (!batch || !info) return fail(GH_EINVAL, "batch and info must be non-NULL");
     memset(info, 0, sizeof(*info));
@@ -781,6 +841,9 @@ int gh_batch_get_info(const gh_batch* batch, gh_batch_info* info) {
     }
     info->sweep_waves = batch->waves;
     info->column_height = batch->nvx_t;
+    info->sweep_locations = batch->loc_tile;
+    info->range_chirps = batch->req_nch;
+    info->doppler_rows = batch->req_nrow;
     info->points = batch->points;
     info->workspace_bytes = (int64_t)batch->ws_used;
     return ok();
@@ -798,7 +861,7 @@ int gh_batch_run(const gh_batch* batch, gh_peak* d_argmax, void* stream) {
                                             batch->wg[0], batch->wg[1], st);
     if (e == hipSuccess)
         e = gh::launch_sweep_batch(t, batch->nf, batch->units[2], batch->interp, batch->nvx_t, batch->wave_f4,
-                                   batch->waves, batch->wg[2], st);
+                                   batch->waves, batch->wg[2], batch->loc_tile, st);
     if (e == hipSuccess && d_argmax) e = gh::launch_peak_batch(t, batch->nf, d_argmax, st);
     if (e != hipSuccess) return hip_fail(e, "gh_batch_run launch");
     return ok();

@@ -2,7 +2,8 @@
 // argmax of eqs. (5)-(6) over many frames of different shapes, each as one
 // persistent launch that walks a device-resident frame-descriptor table.
 //
-// Sweep: a work unit is one location of one frame, owned by one wave.  The
+// Sweep: a work unit is a tile of loc_tile consecutive locations of one frame
+// (one by default), owned by one wave, which takes them in turn.  The
 // wave keeps its FastGeo records and its receiver's Doppler table in a private
 // LDS slice (sized for the batch's largest N_d), so the waves of a workgroup
 // never synchronise with each other.  Lane (part, ivy) owns the vy column ivy
@@ -24,7 +25,7 @@ constexpr int kGeoF4 = (int)(sizeof(FastGeo) / sizeof(float4)) * kMaxRx;   // Fa
 
 template <int INTERP, int NVX>
 __global__ __launch_bounds__(64 * kMaxWaves) void sweep_batch(const FrameDesc* __restrict__ frames, int nf, int total,
-                                                              int wave_f4) {
+                                                              int wave_f4, int loc_tile) {
     extern __shared__ float4 lds[];
     constexpr int kRun = INTERP ? 4 : 2;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -37,8 +38,9 @@ __global__ __launch_bounds__(64 * kMaxWaves) void sweep_batch(const FrameDesc* _
     for (int u = blockIdx.x * wpb + wid; u < total; u += stride) {
         while (f + 1 < nf && frames[f + 1].unit0[2] <= u) ++f;
         const FrameDesc* fd = frames + f;
-        const int loc = u - fd->unit0[2];
-        if (loc >= fd->nunit[2]) continue;   // not reached for a consistent table
+        const int tile = u - fd->unit0[2];
+        if (tile >= fd->nunit[2]) continue;   // not reached for a consistent table
+        for (int loc = tile * loc_tile; loc < (tile + 1) * loc_tile && loc < fd->gp.nloc; ++loc) {
         const int k = fd->g.k, nd = fd->g.nd, log2nd = fd->g.log2_nd;
         const int log2p = log2nd > 9 ? log2nd : 9;   // 2^32 = 2^log2p Doppler bins
         const float sd = fd->g.sign_d;
@@ -112,6 +114,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void sweep_batch(const FrameDesc* _
             p.index = (int64_t)loc * nv + (bi == 0x7fffffff ? 0 : bi);
             as_global(fd->block)[loc] = p;
         }
+        }   // locations of the tile
     }
 }
 
@@ -136,22 +139,22 @@ __global__ __launch_bounds__(1024) void peak_batch(const FrameDesc* __restrict__
 }
 
 template <int INTERP, int NVX>
-hipError_t launch_nvx(int nf, int units, int wave_f4, int waves, int workgroups, const FrameDesc* frames,
-                      hipStream_t st) {
+hipError_t launch_nvx(int nf, int units, int wave_f4, int waves, int workgroups, int loc_tile,
+                      const FrameDesc* frames, hipStream_t st) {
     const size_t lds = (size_t)waves * wave_f4 * sizeof(float4);
     hipLaunchKernelGGL((sweep_batch<INTERP, NVX>), dim3(workgroups), dim3(64 * waves), lds, st, frames, nf, units,
-                       wave_f4);
+                       wave_f4, loc_tile);
     return hipGetLastError();
 }
 
 template <int INTERP>
-hipError_t launch_interp(int nvx_t, int nf, int units, int wave_f4, int waves, int workgroups,
+hipError_t launch_interp(int nvx_t, int nf, int units, int wave_f4, int waves, int workgroups, int loc_tile,
                          const FrameDesc* frames, hipStream_t st) {
     switch (nvx_t) {
-        case 4: return launch_nvx<INTERP, 4>(nf, units, wave_f4, waves, workgroups, frames, st);
-        case 8: return launch_nvx<INTERP, 8>(nf, units, wave_f4, waves, workgroups, frames, st);
-        case 16: return launch_nvx<INTERP, 16>(nf, units, wave_f4, waves, workgroups, frames, st);
-        default: return launch_nvx<INTERP, 32>(nf, units, wave_f4, waves, workgroups, frames, st);
+        case 4: return launch_nvx<INTERP, 4>(nf, units, wave_f4, waves, workgroups, loc_tile, frames, st);
+        case 8: return launch_nvx<INTERP, 8>(nf, units, wave_f4, waves, workgroups, loc_tile, frames, st);
+        case 16: return launch_nvx<INTERP, 16>(nf, units, wave_f4, waves, workgroups, loc_tile, frames, st);
+        default: return launch_nvx<INTERP, 32>(nf, units, wave_f4, waves, workgroups, loc_tile, frames, st);
     }
 }
 
@@ -194,11 +197,12 @@ int sweep_batch_max_workgroups(int interp, int nvx_t, int waves, size_t lds) {
 }
 
 hipError_t launch_sweep_batch(const FrameDesc* frames, int nf, int units, int interp, int nvx_t, int wave_f4,
-                              int waves, int workgroups, hipStream_t st) {
+                              int waves, int workgroups, int loc_tile, hipStream_t st) {
     const int need = (units + waves - 1) / waves;
     if (workgroups > need) workgroups = need;
-    if (interp == GH_INTERP_BICUBIC) return launch_interp<1>(nvx_t, nf, units, wave_f4, waves, workgroups, frames, st);
-    return launch_interp<0>(nvx_t, nf, units, wave_f4, waves, workgroups, frames, st);
+    if (interp == GH_INTERP_BICUBIC)
+        return launch_interp<1>(nvx_t, nf, units, wave_f4, waves, workgroups, loc_tile, frames, st);
+    return launch_interp<0>(nvx_t, nf, units, wave_f4, waves, workgroups, loc_tile, frames, st);
 }
 
 hipError_t launch_peak_batch(const FrameDesc* frames, int nf, gh_peak* argmax, hipStream_t st) {

@@ -325,6 +325,8 @@ hipError_t launch_rd_maps(const Geom& g, const float2* y, void* maps, int map_dt
 // lds1), nrow range rows per Doppler workgroup (LDS lds2, pre-twiddles in LDS
 // when pre_lds).
 void rd_maps_plan(const Geom& g, int& nch, size_t& lds1, int& nrow, int& pre_lds, size_t& lds2);
+// The same for a requested nch and nrow (powers of two), clamped in place.
+void rd_maps_shape(const Geom& g, int& nch, int& nrow, size_t& lds1, int& pre_lds, size_t& lds2);
 
 // Batch launches (frames: device table of nf descriptors).  Workgroup counts
 // are the persistent grid sizes; each launch clamps them to its unit count.
@@ -337,7 +339,7 @@ int sweep_batch_slice_f4(int interp, int nd_max);
 bool sweep_batch_nvx(int chunk_max, int& nvx_t);
 int sweep_batch_max_workgroups(int interp, int nvx_t, int waves, size_t lds);
 hipError_t launch_sweep_batch(const FrameDesc* frames, int nf, int units, int interp, int nvx_t, int wave_f4,
-                              int waves, int workgroups, hipStream_t st);
+                              int waves, int workgroups, int loc_tile, hipStream_t st);
 hipError_t launch_peak_batch(const FrameDesc* frames, int nf, gh_peak* argmax, hipStream_t st);
 int range_batch_max_workgroups(size_t lds);
 int doppler_batch_max_workgroups(size_t lds);

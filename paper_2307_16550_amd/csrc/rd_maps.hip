@@ -32,6 +32,13 @@ namespace gh {
 namespace {
 
 constexpr int kThreads = 512;
+
+// Complex product with the fused multiply-adds spelled out, so that every pass
+// below (workgroup-wide or one transform per wave, single frames or batches)
+// rounds the same way and their maps agree bit for bit.
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
+}
 constexpr int kBuf = 4096;        // complex values of FFT work per workgroup
 constexpr int kBfly = kBuf / 2 / kThreads;   // butterflies per thread and stage, at most
 
@@ -90,10 +97,10 @@ __device__ void lds_fft(float2* buf, int nseq, int stride, int log2m, const floa
                 // twiddle exponent jm * m / (ns * radix)
                 const int tstep = jm << (log2m - log2ns - log2r);
                 const float2 a0 = base[j];
-                const float2 a1 = cmul(base[j + per_seq], tw[tstep]);
+                const float2 a1 = cmulf(base[j + per_seq], tw[tstep]);
                 if (log2r == 2) {
-                    const float2 a2 = cmul(base[j + 2 * per_seq], tw[2 * tstep]);
-                    const float2 a3 = cmul(base[j + 3 * per_seq], tw[3 * tstep]);
+                    const float2 a2 = cmulf(base[j + 2 * per_seq], tw[2 * tstep]);
+                    const float2 a3 = cmulf(base[j + 3 * per_seq], tw[3 * tstep]);
                     const float2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
                     const float2 s13 = cadd(a1, a3), d13 = csub(a1, a3);
                     const float2 jd13 = make_float2(d13.y, -d13.x);   // -j * d13
@@ -163,10 +170,10 @@ __device__ void wave_fft(float2* buf, int nseq, int stride, int log2m, const flo
                 const float2* base = buf + seq * stride;
                 const int tstep = jm << (log2m - log2ns - log2r);
                 const float2 a0 = base[j];
-                const float2 a1 = cmul(base[j + per_seq], tw[tstep]);
+                const float2 a1 = cmulf(base[j + per_seq], tw[tstep]);
                 if (log2r == 2) {
-                    const float2 a2 = cmul(base[j + 2 * per_seq], tw[2 * tstep]);
-                    const float2 a3 = cmul(base[j + 3 * per_seq], tw[3 * tstep]);
+                    const float2 a2 = cmulf(base[j + 2 * per_seq], tw[2 * tstep]);
+                    const float2 a3 = cmulf(base[j + 3 * per_seq], tw[3 * tstep]);
                     const float2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
                     const float2 s13 = cadd(a1, a3), d13 = csub(a1, a3);
                     const float2 jd13 = make_float2(d13.y, -d13.x);   // -j * d13
@@ -229,7 +236,7 @@ __device__ __forceinline__ void range_unit(const Geom& g, int nch, size_t row_by
         const int e = threadIdx.x + j * kThreads;
         if (e < nch * ms) {
             const int c = e >> g.log2_ms, s = e & (ms - 1);
-            buf[c * stride + s] = cmul(x[j], pre[s]);
+            buf[c * stride + s] = cmulf(x[j], pre[s]);
         }
     }
     __syncthreads();
@@ -238,7 +245,7 @@ __device__ __forceinline__ void range_unit(const Geom& g, int nch, size_t row_by
     const int log2n = 31 - __clz(nch);
     for (int e = threadIdx.x; e < nch * ms; e += kThreads) {
         const int c = e & (nch - 1), k = e >> log2n;
-        const float2 v = cmul(buf[c * stride + k], cen[k]);
+        const float2 v = cmulf(buf[c * stride + k], cen[k]);
         float2* row = reinterpret_cast<float2*>(maps + ((size_t)q * g.nr + (size_t)k * g.pr + p) * row_bytes);
         row[m0 + c] = v;
     }
@@ -283,7 +290,7 @@ __device__ __forceinline__ void doppler_unit(const Geom& g, int nrow, int pre_ld
             const int r = e >> g.log2_mc, m = e & (mc - 1);
             for (int p = 0; p < pd; ++p) {
                 const float2 w = pre_lds ? pre[p * mc + m] : expm_pi((long long)p * (2LL * m - c2), nd);
-                buf[(r * pd + p) * stride + m] = cmul(x[j], w);
+                buf[(r * pd + p) * stride + m] = cmulf(x[j], w);
             }
         }
     }
@@ -294,7 +301,7 @@ __device__ __forceinline__ void doppler_unit(const Geom& g, int nrow, int pre_ld
     for (int e = threadIdx.x; e < nrow * nd; e += kThreads) {
         const int r = e >> g.log2_nd, l = e & (nd - 1);
         const int k = l >> log2pd, p = l & (pd - 1);
-        const float2 v = cmul(buf[(r * pd + p) * stride + k], cen[k]);
+        const float2 v = cmulf(buf[(r * pd + p) * stride + k], cen[k]);
         char* row = rowb + (size_t)r * row_bytes;
         if constexpr (DT == GH_MAP_C64) {
             reinterpret_cast<float2*>(row)[l] = v;
@@ -344,7 +351,7 @@ __global__ __launch_bounds__(kThreads) void range_pass_w(Geom g, size_t row_byte
 #pragma unroll
     for (int j = 0; j < NP / 64; ++j) {
         const int s = lane + 64 * j;
-        if (s < ms) bw[s] = cmul(x[j], pre[s]);
+        if (s < ms) bw[s] = cmulf(x[j], pre[s]);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -354,7 +361,7 @@ __global__ __launch_bounds__(kThreads) void range_pass_w(Geom g, size_t row_byte
     const int log2n = 31 - __clz(nw);
     for (int e = threadIdx.x; e < nw * ms; e += blockDim.x) {
         const int c = e & (nw - 1), k = e >> log2n;
-        const float2 v = cmul(buf[c * stride + k], cen[k]);
+        const float2 v = cmulf(buf[c * stride + k], cen[k]);
         float2* row = reinterpret_cast<float2*>(maps + ((size_t)q * g.nr + (size_t)k * g.pr + p) * row_bytes);
         row[m0 + c] = v;
     }
@@ -392,7 +399,7 @@ __global__ __launch_bounds__(kThreads) void doppler_pass_w(Geom g, char* __restr
     for (int j = 0; j < NP / 64; ++j) {
         const int m = lane + 64 * j;
         if (m < mc)
-            for (int p = 0; p < pd; ++p) bw[p * stride + m] = cmul(x[j], pre[p * mc + m]);
+            for (int p = 0; p < pd; ++p) bw[p * stride + m] = cmulf(x[j], pre[p * mc + m]);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -401,7 +408,7 @@ __global__ __launch_bounds__(kThreads) void doppler_pass_w(Geom g, char* __restr
     const float inv_scale = 1.f / map_scale(g.ms, mc, DT);
     for (int l = lane; l < nd; l += 64) {
         const int k = l >> log2pd, p = l & (pd - 1);
-        const float2 v = cmul(bw[p * stride + k], cen[k]);
+        const float2 v = cmulf(bw[p * stride + k], cen[k]);
         if constexpr (DT == GH_MAP_C64) {
             reinterpret_cast<float2*>(row)[l] = v;
         } else {
@@ -500,10 +507,21 @@ void rd_maps_plan(const Geom& g, int& nch, size_t& lds1, int& nrow, int& pre_lds
     nch = kBuf / g.ms;
     if (nch > g.mc) nch = g.mc;
     while (nch > 8 && (long)(g.mc / nch) * g.pr * g.k < 512) nch >>= 1;
-    lds1 = ((size_t)nch * (g.ms + 1) + 3 * (size_t)g.ms) * sizeof(float2);
     nrow = kBuf / g.nd;
-    if (nrow < 1) nrow = 1;
+    rd_maps_shape(g, nch, nrow, lds1, pre_lds, lds2);
+}
+
+// Clamps nch and nrow (powers of two) to what one workgroup holds (nch Ms and
+// nrow N_d at most kBuf values, no more than the frame) and gives the LDS of
+// both passes.
+void rd_maps_shape(const Geom& g, int& nch, int& nrow, size_t& lds1, int& pre_lds, size_t& lds2) {
+    if (nch > kBuf / g.ms) nch = kBuf / g.ms;
+    if (nch > g.mc) nch = g.mc;
+    if (nch < 1) nch = 1;
+    if (nrow > kBuf / g.nd) nrow = kBuf / g.nd;
     if (nrow > g.nr) nrow = g.nr;
+    if (nrow < 1) nrow = 1;
+    lds1 = ((size_t)nch * (g.ms + 1) + 3 * (size_t)g.ms) * sizeof(float2);
     lds2 = ((size_t)nrow * g.pd * (g.mc + 1) + 2 * (size_t)g.mc) * sizeof(float2);
     pre_lds = lds2 + (size_t)g.nd * sizeof(float2) <= 65536 ? 1 : 0;
     if (pre_lds) lds2 += (size_t)g.nd * sizeof(float2);

@@ -29,7 +29,8 @@ EXPORTS = ("gh_abi_version", "gh_last_error", "gh_rd_maps", "gh_decision", "gh_a
            "gh_refine_workspace_bytes",
            "gh_refine", "gh_refine_noalloc", "gh_direct_points_workspace_bytes", "gh_direct_points", "gh_gh_points",
            "gh_range_spectra", "gh_factored_workspace_bytes", "gh_factored_decision",
-           "gh_batch_workspace_bytes", "gh_batch_create", "gh_batch_tune", "gh_batch_get_info", "gh_batch_run",
+           "gh_batch_workspace_bytes", "gh_batch_create", "gh_batch_tune", "gh_batch_tune_tiles", "gh_batch_get_info",
+           "gh_batch_run",
            "gh_batch_frame_maps", "gh_batch_destroy", "gh_test_set_knob")
 
 
@@ -56,7 +57,8 @@ class GhFrame(ctypes.Structure):
 class GhBatchInfo(ctypes.Structure):
     _fields_ = [("n_frames", ctypes.c_int32), ("interp", ctypes.c_int32), ("units", ctypes.c_int32 * 3),
                 ("workgroups", ctypes.c_int32 * 3), ("max_workgroups", ctypes.c_int32 * 3),
-                ("sweep_waves", ctypes.c_int32), ("column_height", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sweep_waves", ctypes.c_int32), ("column_height", ctypes.c_int32),
+                ("sweep_locations", ctypes.c_int32), ("range_chirps", ctypes.c_int32), ("doppler_rows", ctypes.c_int32),
                 ("points", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
 
 
@@ -112,6 +114,7 @@ def load():
     lib.gh_batch_workspace_bytes.restype = sz
     lib.gh_batch_create.argtypes = [fp, i32, i32, vp, sz, ctypes.POINTER(ctypes.c_void_p), vp]
     lib.gh_batch_tune.argtypes = [vp, i32, i32, i32, i32]
+    lib.gh_batch_tune_tiles.argtypes = [vp, i32, i32, i32, vp]
     lib.gh_batch_get_info.argtypes = [vp, ctypes.POINTER(GhBatchInfo)]
     lib.gh_batch_run.argtypes = [vp, pp, vp]
     lib.gh_batch_frame_maps.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_void_p)]
@@ -119,7 +122,7 @@ def load():
     lib.gh_batch_destroy.restype = None
     for name in ("gh_rd_maps", "gh_decision", "gh_argmax", "gh_direct_decision", "gh_bomp_step", "gh_bomp_select",
                  "gh_bomp_seed", "gh_bomp_fit", "gh_refine", "gh_refine_noalloc",
-                 "gh_direct_points", "gh_gh_points", "gh_range_spectra", "gh_factored_decision", "gh_batch_create", "gh_batch_tune", "gh_batch_get_info",
+                 "gh_direct_points", "gh_gh_points", "gh_range_spectra", "gh_factored_decision", "gh_batch_create", "gh_batch_tune", "gh_batch_tune_tiles", "gh_batch_get_info",
                  "gh_batch_run", "gh_batch_frame_maps"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -560,11 +563,19 @@ class Batch:
         _check(load().gh_batch_get_info(self._h, ctypes.byref(inf)))
         return dict(n_frames=inf.n_frames, interp=inf.interp, units=list(inf.units),
                     workgroups=list(inf.workgroups), max_workgroups=list(inf.max_workgroups),
-                    sweep_waves=inf.sweep_waves, column_height=inf.column_height, points=inf.points,
+                    sweep_waves=inf.sweep_waves, column_height=inf.column_height,
+                    sweep_locations=inf.sweep_locations, range_chirps=inf.range_chirps,
+                    doppler_rows=inf.doppler_rows, points=inf.points,
                     workspace_bytes=inf.workspace_bytes)
 
     def tune(self, range_wg=0, doppler_wg=0, sweep_wg=0, sweep_waves=0):
         _check(load().gh_batch_tune(self._h, int(range_wg), int(doppler_wg), int(sweep_wg), int(sweep_waves)))
+
+    def tune_tiles(self, range_chirps=0, doppler_rows=0, sweep_locations=0, stream=None):
+        """Map-pass tiles (0: each frame's planner) and locations per sweep unit (0 keeps);
+        re-plans the work units and resets the map passes' workgroup counts."""
+        _check(load().gh_batch_tune_tiles(self._h, int(range_chirps), int(doppler_rows), int(sweep_locations),
+                                          _stream(stream)))
 
     def run(self, want_argmax=True, stream=None) -> torch.Tensor:
         _check(load().gh_batch_run(self._h, _ptr(self.argmax) if want_argmax else None, _stream(stream)))
@@ -600,12 +611,15 @@ class Batch:
             pass
 
 
-def autotune(batch: Batch, reps=3, factors=(0.25, 0.5, 1.0, 2.0)) -> dict:
-    """Coordinate search of the batch's persistent launch shapes: sweep waves per
-    workgroup and sweep workgroups (as factors of the resident maximum), then the
-    range and Doppler workgroups, each timed over `reps` runs with HIP events on
-    the current stream.  Leaves the fastest setting applied; returns it with
-    every trial ({"best": {...}, "ms": float, "trials": [...]})."""
+def autotune(batch: Batch, reps=3, factors=(0.25, 0.5, 1.0, 2.0), range_chirps=(0, 4, 8, 16),
+             doppler_rows=(0, 1, 2, 4, 8), sweep_locations=(1, 2, 4)) -> dict:
+    """Coordinate search of the batch's launch shapes: the tiles first (locations
+    per sweep unit, then range chirps and Doppler rows per map workgroup, 0 being
+    each frame's planner), then sweep waves per workgroup and sweep workgroups
+    (as factors of the resident maximum), then the range and Doppler workgroups,
+    each setting timed over `reps` runs with HIP events on the current stream.
+    Leaves the fastest setting applied; returns it with every trial
+    ({"best": {...}, "ms": float, "trials": [...]})."""
     def timed():
         batch.run()
         start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -617,6 +631,32 @@ def autotune(batch: Batch, reps=3, factors=(0.25, 0.5, 1.0, 2.0)) -> dict:
         return start.elapsed_time(end) / reps
 
     trials = []
+    # tiles: each change re-plans the work units and resets the map workgroups to the maximum
+    tiles = dict(range_chirps=batch.info()["range_chirps"], doppler_rows=batch.info()["doppler_rows"],
+                 sweep_locations=batch.info()["sweep_locations"])
+    tiles_ms = None
+
+    def try_tiles(**kw):
+        nonlocal tiles, tiles_ms
+        cand = dict(tiles, **kw)
+        try:
+            batch.tune_tiles(cand["range_chirps"], cand["doppler_rows"], cand["sweep_locations"])
+        except GridHopError:
+            return
+        ms = timed()
+        trials.append(dict(cand, ms=ms))
+        if tiles_ms is None or ms < tiles_ms:
+            tiles, tiles_ms = cand, ms
+
+    try_tiles()
+    for v in sweep_locations:
+        try_tiles(sweep_locations=v)
+    for v in range_chirps:
+        try_tiles(range_chirps=v)
+    for v in doppler_rows:
+        try_tiles(doppler_rows=v)
+    batch.tune_tiles(tiles["range_chirps"], tiles["doppler_rows"], tiles["sweep_locations"])
+
     inf = batch.info()
     best = dict(range_wg=inf["workgroups"][0], doppler_wg=inf["workgroups"][1], sweep_wg=inf["workgroups"][2],
                 sweep_waves=inf["sweep_waves"])
@@ -648,4 +688,4 @@ def autotune(batch: Batch, reps=3, factors=(0.25, 0.5, 1.0, 2.0)) -> dict:
         for fct in factors:
             consider(**{key: max(1, int(m * fct))})
     batch.tune(best["range_wg"], best["doppler_wg"], best["sweep_wg"], best["sweep_waves"])
-    return dict(best=best, ms=best_ms, trials=trials)
+    return dict(best=dict(best, **tiles), ms=best_ms, trials=trials)

@@ -242,8 +242,13 @@ def batch_frames(specs):
 def test_batch_struct_layout():
     # gh_frame: gh_radar (4 doubles, 6 int32, tx[2], rx pointer = 80 bytes), gh_grid (80), 3 pointers
     assert ctypes.sizeof(gh.GhFrame) == 184 and gh.GhFrame.d_y.offset == 160
-    # gh_batch_info: 14 int32, then two int64
-    assert ctypes.sizeof(gh.GhBatchInfo) == 72 and gh.GhBatchInfo.points.offset == 56
+    # gh_batch_info: 16 int32, then two int64
+    assert ctypes.sizeof(gh.GhBatchInfo) == 80 and gh.GhBatchInfo.points.offset == 64
+
+
+def test_batch_tune_tiles_argument_checks(lib):
+    assert lib.gh_batch_tune_tiles(None, 0, 0, 1, None) == gh.GH_EINVAL
+    assert "batch is NULL" in gh.last_error()
 
 
 def test_batch_argument_checks(lib):

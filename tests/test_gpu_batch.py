@@ -193,11 +193,31 @@ def test_batch_results_independent_of_launch_shape():
         for t, r in zip(b.blocks, ref[1]):
             assert torch.equal(t, r)
         assert torch.equal(b.argmax, ref[2])
+    # tiles of the map passes and of the sweep: re-planned work units, same results
+    for tiles in [(1, 1, 1), (4, 2, 3), (64, 16, 8), (0, 0, 64), (2, 4096, 1)]:
+        b.tune_tiles(*tiles)
+        b.run()
+        torch.cuda.synchronize()
+        inf = b.info()
+        say(f"tiles {tiles}: units {inf['units']} workgroups {inf['workgroups']}")
+        assert inf["sweep_locations"] == (tiles[2] if tiles[2] else inf["sweep_locations"])
+        for t, r in zip(b.decs, ref[0]):
+            assert torch.equal(t, r)
+        for t, r in zip(b.blocks, ref[1]):
+            assert torch.equal(t, r)
+        assert torch.equal(b.argmax, ref[2])
+    with pytest.raises(gh.GridHopError):
+        b.tune_tiles(3, 0, 0)          # not a power of two
+    with pytest.raises(gh.GridHopError):
+        b.tune_tiles(0, 0, 65)         # more than 64 locations per unit
+    b.tune_tiles(0, 0, 1)
     res = gh.autotune(b, reps=2)
     say(f"autotune best {res['best']} {res['ms']:.3f} ms over {len(res['trials'])} trials")
     b.run()
     torch.cuda.synchronize()
     assert torch.equal(b.argmax, ref[2])
+    for t, r in zip(b.blocks, ref[1]):
+        assert torch.equal(t, r)
     b.close()
 
 
