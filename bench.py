@@ -680,8 +680,8 @@ def main():
 
     if not args.no_cpu_baseline and not args.step_only:
         rng = np.random.default_rng(2024)
-        gh_idx = rng.integers(0, n_gh, 2_000_000)
-        dir_idx = rng.integers(0, n_dir, 100_000)
+        gh_idx = rng.integers(0, n_gh, 4_000_000)     # about 10 s of one core's oracle work in all
+        dir_idx = rng.integers(0, n_dir, 200_000)
         torch.cuda.synchronize()
         dv = dec.view(-1).cpu().numpy()
         ddv = ddec.view(-1).cpu().numpy()
