@@ -587,11 +587,13 @@ constexpr int kCandV = 2;            // points per sweep of a row on the VALU pa
 constexpr int kInFlight = 4;         // frame loads in flight per lane
 constexpr int kWgsTarget = 32;       // preferred workgroups per cell
 constexpr int kErMax = 4096;         // range phase factors per pass (64 KB of LDS)
+constexpr size_t kLdsBytes = 160 * 1024;   // LDS of one workgroup on gfx950
 constexpr int kSlotsMax = 4096;      // workgroups per launch (partial-buffer slots)
 constexpr unsigned kSpinLimit = 1u << 21;
 
 struct Cluster {
     int rows_per_wg;   // R, a power of two (a divisor or a multiple of Mc)
+    int ystage;        // the workgroup's frame rows staged in LDS after the range table (0: read from memory)
     int wgs;           // W = ceil(K Mc / R)
     int slots;         // partial-buffer slots (workgroups of one launch)
     unsigned spin_limit;   // polls before a barrier wait expires
@@ -644,16 +646,24 @@ struct ClusterCtx {
 
 // The matrix-core per-row sums apply when every row of a workgroup belongs to
 // one receiver, the rows form 16-row tiles and the samples 32- or 64-sample steps.
+// Sample parts of the tiles: as many as the idle waves allow (1, 2 or 4), each
+// part a multiple of 32 samples.
+__device__ __forceinline__ int mfma_parts(int ntiles, int ms) {
+    int kp = 1;
+    while (kp < 4 && ntiles * kp * 2 <= kCT / 64 && ms % (32 * kp * 2) == 0) kp *= 2;
+    return kp;
+}
+
 __device__ __forceinline__ bool mfma_rows(const Cluster& cl, int ms, const ClusterCtx& cx) {
     const int R = cl.rows_per_wg;
     const int ntiles = (R >> 4) * 2;
-    const int kparts = ntiles >= kCT / 64 ? 1 : 2;
-    return cx.nq == 1 && R % 16 == 0 && ntiles * kparts <= kCT / 64 && ms % (32 * kparts) == 0;
+    return cx.nq == 1 && R % 16 == 0 && ntiles <= kCT / 64 && ms % 32 == 0;
 }
 
 // One pass at the points sh.th[0 .. npts): leaves all six moments of every
 // receiver at each point in sh.mom.  er: LDS table of range phase factors.
-__device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx& cx, const float2* __restrict__ y,
+// ysrc: the workgroup's first frame row (in LDS or memory), rows ystride apart.
+__device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx& cx, const float2* ysrc, int ystride,
                              double2* er, int npts, unsigned& pass, ClusterShared& sh, unsigned* ctr,
                              unsigned* abort_flag, double* __restrict__ part) {
     const int tid = threadIdx.x;
@@ -667,10 +677,13 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
     }
     __syncthreads();
     const int nte = cx.nq * ms;
+    // one padded row per point: the matrix-core reads of the eight points' rows at
+    // one sample fall in distinct banks
+    const int ers = nte + 1;
     for (int e = tid; e < npts * nte; e += kCT) {
         const int c = e / nte, r = e - c * nte;
         const int i = r >> g.log2_ms, s = r & (ms - 1);
-        er[e] = expm_fixed64(sh.fr[c][i] * (uint64_t)s);
+        er[c * ers + r] = expm_fixed64(sh.fr[c][i] * (uint64_t)s);
     }
     for (int e = tid; e < npts * cx.nrows; e += kCT) {
         const int c = e / cx.nrows, r = e - c * cx.nrows;
@@ -684,11 +697,12 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
         // points take the VALU path below): C[row][col] = sum_s Y[row][s] B[s][col], col = 8 p + c,
         // B[s][col] = s^p e_c[s] (columns 24..31 zero), as 16 x 16 complex tiles.
         // The (R / 16) x 2 tiles go to waves t + ntiles h, h < kparts, each over
-        // its part of the samples; part 0 stores, part 1 then adds (fixed order).
+        // its part of the samples; part 0 stores, parts 1, 2, ... then add in
+        // turn (fixed order).
         const int wave = tid >> 6, lane = tid & 63;
         const int r = lane & 15, grp = lane >> 4;
         const int ntiles = (R >> 4) * 2;
-        const int kparts = ntiles >= kCT / 64 ? 1 : 2;
+        const int kparts = mfma_parts(ntiles, ms);
         const int h = wave / ntiles, t = wave - h * ntiles;
         const bool active = h < kparts;
         f64x4 cre = {0.0, 0.0, 0.0, 0.0}, cim = {0.0, 0.0, 0.0, 0.0};
@@ -696,8 +710,8 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
             const int row = (t >> 1) * 16 + r, col = (t & 1) * 16 + r;
             const int pw = col >> 3, c = col & 7;
             const bool rowv = row < cx.nrows, colv = col < 24 && c < npts;
-            const float2* yr = y + (size_t)(cx.r0 + (rowv ? row : 0)) * ms;
-            const double2* ec = er + c * ms;
+            const float2* yr = ysrc + (size_t)(rowv ? row : 0) * ystride;
+            const double2* ec = er + c * ers;
             const int span = ms / kparts;
             for (int s0 = h * span; s0 < (h + 1) * span; s0 += 32) {
                 const int sb = s0 + grp * 8;
@@ -724,12 +738,14 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
 #pragma unroll
             for (int sl = 0; sl < 4; ++sl) sh.a[c_out][p_out][(t >> 1) * 16 + 4 * sl + grp] = make_double2(cre[sl], cim[sl]);
         }
-        __syncthreads();
-        if (active && h == 1 && j < 24) {
+        for (int hh = 1; hh < kparts; ++hh) {
+            __syncthreads();
+            if (active && h == hh && j < 24) {
 #pragma unroll
-            for (int sl = 0; sl < 4; ++sl) {
-                double2& d = sh.a[c_out][p_out][(t >> 1) * 16 + 4 * sl + grp];
-                d = make_double2(d.x + cre[sl], d.y + cim[sl]);
+                for (int sl = 0; sl < 4; ++sl) {
+                    double2& d = sh.a[c_out][p_out][(t >> 1) * 16 + 4 * sl + grp];
+                    d = make_double2(d.x + cre[sl], d.y + cim[sl]);
+                }
             }
         }
     } else {
@@ -743,7 +759,7 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
 #pragma unroll
                 for (int i = 0; i < 6; ++i) acc[c][i] = 0.0;
             if (row < cx.nrows) {
-                const float2* yr = y + (size_t)(cx.r0 + row) * ms;
+                const float2* yr = ysrc + (size_t)row * ystride;
                 const int eoff = (((cx.r0 + row) >> g.log2_mc) - cx.q_lo) * ms;
                 // kInFlight independent loads per lane, then their products (in sample order)
                 for (int s0 = lane; s0 < ms; s0 += kInFlight * tpr) {
@@ -762,7 +778,7 @@ __device__ bool cluster_pass(const Geom& g, const Cluster& cl, const ClusterCtx&
 #pragma unroll
                             for (int c = 0; c < kCandV; ++c) {
                                 if (c0 + c < npts) {
-                                    const double2 e = er[(c0 + c) * nte + eoff + s];
+                                    const double2 e = er[(c0 + c) * ers + eoff + s];
                                     const double re = fma(vx, e.x, -vy * e.y);
                                     const double im = fma(vx, e.y, vy * e.x);
                                     acc[c][0] += re;
@@ -884,6 +900,20 @@ __global__ __launch_bounds__(kCT) void refine_cluster_kernel(Geom g, GridP gp, c
     cx.nrows = min(cl.rows_per_wg, rows - cx.r0);
     cx.q_lo = cx.r0 >> g.log2_mc;
     cx.nq = cl.rows_per_wg <= g.mc ? 1 : (cx.nrows + g.mc - 1) >> g.log2_mc;
+    // the workgroup's frame rows: read by every pass, so staged once in LDS when they fit
+    // (rows padded by 16 bytes: the matrix-core reads of 16 rows fall in distinct banks)
+    const float2* ysrc = y + (size_t)cx.r0 * g.ms;
+    int ystride = g.ms;
+    if (cl.ystage) {
+        const int ers = cx.nq * g.ms + 1;
+        float2* ys = reinterpret_cast<float2*>(er + kCand * ers);
+        ystride = g.ms + 2;
+        for (int e = tid; e < cx.nrows * g.ms; e += kCT) {
+            const int r = e >> g.log2_ms, s = e & (g.ms - 1);
+            ys[r * ystride + s] = ysrc[e];
+        }
+        ysrc = ys;
+    }
     double th0[4];
     start_point(gp, cells[cx.cell], th0);
     const double h[4] = {gp.step[0], gp.step[1], gp.step[2], gp.step[3]};
@@ -891,7 +921,7 @@ __global__ __launch_bounds__(kCT) void refine_cluster_kernel(Geom g, GridP gp, c
     unsigned pass = 0;
     if (tid < 4) sh.th[0][tid] = th0[tid];
     __syncthreads();
-    bool ok = cluster_pass(g, cl, cx, y, er, 1, pass, sh, ctr, abort_flag, part);
+    bool ok = cluster_pass(g, cl, cx, ysrc, ystride, er, 1, pass, sh, ctr, abort_flag, part);
     double d_cur = point_value(g, sh.mom[0]);
     for (int e = tid; e < g.k * 12; e += kCT) sh.cur[e / 12][e % 12] = sh.mom[0][e / 12][e % 12];
     __syncthreads();
@@ -933,7 +963,7 @@ __global__ __launch_bounds__(kCT) void refine_cluster_kernel(Geom g, GridP gp, c
                     step[a] *= (c < npts) ? 0.5 : 1.0;
                 }
             __syncthreads();
-            if (!(ok = cluster_pass(g, cl, cx, y, er, npts, pass, sh, ctr, abort_flag, part))) break;
+            if (!(ok = cluster_pass(g, cl, cx, ysrc, ystride, er, npts, pass, sh, ctr, abort_flag, part))) break;
             for (int c = 0; c < npts; ++c)
                 if (point_value(g, sh.mom[c]) >= d_cur) {
                     acc_c = c;
@@ -979,6 +1009,7 @@ Cluster cluster_plan(const Geom& g, int rows_per_wg, int ncells) {
     Cluster cl;
     const int rows = g.k * g.mc;
     cl.rows_per_wg = rows_per_wg;
+    cl.ystage = 0;
     cl.wgs = (rows + rows_per_wg - 1) / rows_per_wg;
     const long slots = (long)ncells * cl.wgs;
     cl.slots = (int)(slots < kSlotsMax ? slots : kSlotsMax);
@@ -1040,8 +1071,12 @@ hipError_t launch_refine_slots(const Geom& g, const GridP& gp, const float2* y, 
     for (int r = rows_pref(g); r <= rows_max(g); r <<= 1) {
         Cluster c = cluster_plan(g, r, ncells);
         const int nq = r <= g.mc ? 1 : r / g.mc;
-        const size_t l = (size_t)kCand * nq * g.ms * sizeof(double2);
-        if (l > (size_t)kErMax * sizeof(double2)) continue;   // the pass's range table does not fit
+        size_t l = (size_t)kCand * (nq * g.ms + 1) * sizeof(double2);
+        if (l > (size_t)(kErMax + kCand) * sizeof(double2)) continue;   // the pass's range table does not fit
+        // the frame rows too, within the device's LDS beside the static part
+        const size_t ly = (size_t)r * (g.ms + 2) * sizeof(float2);
+        c.ystage = (l + ly + sizeof(ClusterShared) + 4096 <= kLdsBytes) ? 1 : 0;   // 4 KB for the rest
+        if (c.ystage) l += ly;
         int per_cu = 0;
         if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
                  &per_cu, reinterpret_cast<const void*>(refine_cluster_kernel), kCT, l)) != hipSuccess)
