@@ -404,20 +404,15 @@ def main():
     # The direct decision (B) is independent of the chain maps -> sweep ->
     # argmax -> Block-OMP -> refinement (A; the sweep is Block-OMP's first
     # selection).  With two streams, A runs on the capture stream; a second
-    # stream (default priority), forked from and joined back into it, runs B
-    # beside it, then, once the last selection is made, the last fit (the
-    # refinement needs only the selections) beside the latency-bound
-    # refinement.
+    # stream (default priority), forked from and joined back into it, waits
+    # for the last selection, then runs the last fit (the refinement needs only
+    # the selections) and B beside the refinement, whose 96 workgroups leave
+    # most of the chip to them.
     side = torch.cuda.Stream(device=dev) if args.streams == 2 else None
 
     def step_two_streams():
         main_s = torch.cuda.current_stream()
-        fork, join = torch.cuda.Event(), torch.cuda.Event()
-        fork.record(main_s)
-        side.wait_event(fork)
-        with torch.cuda.stream(side):
-            gh.direct_decision(radar, dgrid, y, ws=ws, dec=ddec, block=dblock, want_argmax=False)
-            gh.argmax(dblock, darg)
+        join = torch.cuda.Event()
         gh.rd_maps(radar, y, fmaps)
         gh.decision(radar, grid, fmaps, interp, dec=dec, block=block, want_argmax=False)
         bomp.reset()
@@ -431,6 +426,8 @@ def main():
         side.wait_event(selected)
         with torch.cuda.stream(side):
             bomp.fit()
+            gh.direct_decision(radar, dgrid, y, ws=ws, dec=ddec, block=dblock, want_argmax=False)
+            gh.argmax(dblock, darg)
         gh.refine(radar, grid, y, bomp.support, theta=theta, ws=rws)
         join.record(side)
         main_s.wait_event(join)

@@ -1,11 +1,11 @@
-"""The whole hot-path step (maps, grid-hopping decision and argmax, direct
-decision and argmax, three Block-OMP steps, refinement) captured once in a HIP
-graph: three replays on new frames, copied into the captured input buffer
-between replays, each equal bit for bit to an eager step on the same frame.
-The step is captured on one stream, and on two: a second stream (default
-priority), forked from and joined back into the capture stream, runs the
-direct decision and the maps beside the Block-OMP iterations, then the last
-Block-OMP fit and the grid-hopping sweep and argmax beside the refinement.
+"""The whole hot-path step as the bench runs it (maps, grid-hopping decision,
+its argmax seeding Block-OMP, direct decision and argmax, three Block-OMP
+iterations, refinement) captured once in a HIP graph: three replays on new
+frames, copied into the captured input buffer between replays, each equal bit
+for bit to an eager step on the same frame.  The step is captured on one
+stream, and on two: a second stream (default priority), forked from the
+capture stream at the last selection and joined back into it, runs the last
+Block-OMP fit and the direct decision and its argmax beside the refinement.
 The eager path itself is checked against the FP64 oracle in test_gpu_parity.py.
 """
 import numpy as np
@@ -28,7 +28,6 @@ def test_step_graph_replays_match_eager(cfg, streams):
     dgrid_s = sc.direct_grid(s, cfg)
     dgrid = gh.grid_of(dgrid_s)
     y = torch.from_numpy(s.y).to(dev)
-    maps = torch.empty((radar.k, radar.nr, radar.nd), dtype=torch.complex64, device=dev)
     dec = torch.empty(tuple(s.grid.n), dtype=torch.float32, device=dev)
     block = gh.peaks_tensor(s.grid.n[0] * s.grid.n[1], dev)
     arg = gh.peaks_tensor(1, dev)
@@ -40,14 +39,17 @@ def test_step_graph_replays_match_eager(cfg, streams):
     theta = torch.empty((3, 4), dtype=torch.float64, device=dev)
     rws = torch.empty(gh.refine_workspace_bytes(radar, grid, 3), dtype=torch.uint8, device=dev)
 
+    maps = bomp.maps     # the frame's maps: the grid-hopping row's and Block-OMP's
+
     def step():
         gh.rd_maps(radar, y, maps)
         gh.decision(radar, grid, maps, gh.BILINEAR, dec=dec, block=block, want_argmax=False)
-        gh.argmax(block, arg)
+        bomp.reset()
+        bomp.seed(block, selected=arg)
         gh.direct_decision(radar, dgrid, y, ws=ws, dec=ddec, block=dblock, want_argmax=False)
         gh.argmax(dblock, darg)
-        bomp.reset()
-        for _ in range(3):
+        bomp.fit()
+        for _ in range(2):
             bomp.step()
         gh.refine(radar, grid, y, bomp.support, theta=theta, ws=rws)
 
@@ -55,24 +57,21 @@ def test_step_graph_replays_match_eager(cfg, streams):
 
     def step_two_streams():
         main_s = torch.cuda.current_stream()
-        fork, join = torch.cuda.Event(), torch.cuda.Event()
-        fork.record(main_s)
-        side.wait_event(fork)
-        with torch.cuda.stream(side):
-            gh.direct_decision(radar, dgrid, y, ws=ws, dec=ddec, block=dblock, want_argmax=False)
-            gh.argmax(dblock, darg)
-            gh.rd_maps(radar, y, maps)
+        join = torch.cuda.Event()
+        gh.rd_maps(radar, y, maps)
+        gh.decision(radar, grid, maps, gh.BILINEAR, dec=dec, block=block, want_argmax=False)
         bomp.reset()
-        for _ in range(2):
-            bomp.step()
+        bomp.seed(block, selected=arg)
+        bomp.fit()
+        bomp.step()
         bomp.select()
         selected = torch.cuda.Event()
         selected.record(main_s)
         side.wait_event(selected)
         with torch.cuda.stream(side):
             bomp.fit()
-            gh.decision(radar, grid, maps, gh.BILINEAR, dec=dec, block=block, want_argmax=False)
-            gh.argmax(block, arg)
+            gh.direct_decision(radar, dgrid, y, ws=ws, dec=ddec, block=dblock, want_argmax=False)
+            gh.argmax(dblock, darg)
         gh.refine(radar, grid, y, bomp.support, theta=theta, ws=rws)
         join.record(side)
         main_s.wait_event(join)
