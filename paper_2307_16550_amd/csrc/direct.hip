@@ -18,16 +18,19 @@
 //   assignment of contraction indices to the k slots is valid if both
 //   operands share it).  The output element (i, j) sits in lane j + 16 (i / 4),
 //   slot i % 4.
-// FP32: a complex product is four real ones,
+// FP32 range zoom: a complex product is four real ones,
 //   Re C += Re A Re B - Im A Im B,  Im C += Re A Im B + Im A Re B;
 // atoms are generated in registers: one exact anchor per run of eight from a
 // 32-bit fixed-point phase (the wrap modulo one cycle is integer overflow),
 // then the recurrence e_{n+1} = e_n exp(-j 2 pi f).
 // BF16 (gemm_dtype BF16): complex products over interleaved (re, im) pairs,
 // two 16x16x32 products per complex tile step; the range zoom stages the frame
-// in LDS once per workgroup and leaves h = G times a chirp in BF16; the Doppler
+// in LDS once per workgroup.
+// Both precisions: the range zoom leaves h = G times a chirp, and the Doppler
 // zoom reads its left operand from a chirp (Toeplitz) table and forms its
-// right one from h and a second chirp table (see the kernels below).
+// right one from h and a second chirp table (see the kernels below).  Slabs
+// of more than 16 velocity tiles, or tables beyond 64 KB of LDS, take the
+// generating Doppler zoom on G instead.
 #include "gh_internal.h"
 
 namespace gh {
@@ -49,6 +52,11 @@ __device__ __forceinline__ void atom_run(uint32_t f, uint32_t n0, float2 ratio, 
 }
 
 __device__ __forceinline__ f32x4 zero4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
+
+// High word of (a * b) mod 2^64 for a 64-bit fixed-point a and a 32-bit integer b.
+__device__ __forceinline__ uint32_t fixed_mul_hi(uint64_t a, uint32_t b) {
+    return (uint32_t)(a >> 32) * b + __umulhi((uint32_t)a, b);
+}
 
 // C += A B for complex operands held as kRun values per lane (layout above).
 template <bool BF16>
@@ -89,9 +97,13 @@ __device__ __forceinline__ void load_run(const float2* __restrict__ p, float2 (&
     }
 }
 
-// Range zoom.  Grid (ceil(Nloc / 64), ceil(Mc / 64), K); wave w of a
+// Range zoom (FP32).  Grid (ceil(Nloc / 64), ceil(Mc / 64), K); wave w of a
 // workgroup owns 16 locations and 64 chirps of receiver blockIdx.z.
-template <bool BF16>
+//   CHIRP = false: G_q[x][m] (complex64 [K][Nloc][Mc]);
+//   CHIRP = true:  h_q[x][m] = G_q[x][m] exp(-j 2 pi (f0 m + (fx + fy) m^2 / 2))
+//                  (complex64 [K][Nloc][Mc]), the right-hand factor of the
+//                  chirp-table Doppler zoom below.
+template <bool CHIRP>
 __global__ __launch_bounds__(kThreads) void direct_range_zoom(Geom g, GridP gp, const float2* __restrict__ y,
                                                              float2* __restrict__ gws) {
     const int lane = threadIdx.x & 63;
@@ -103,12 +115,17 @@ __global__ __launch_bounds__(kThreads) void direct_range_zoom(Geom g, GridP gp, 
     const int ms = g.ms, mc = g.mc;
 
     uint32_t fr = 0;
+    uint64_t f0l = 0, hsl = 0;
     if (loc0 + r < gp.nloc) {
         const int loc = loc0 + r;
         const int ix = loc / gp.n[1], iy = loc - ix * gp.n[1];
         double rr, wx, wy;
         bistatic(g, q, gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], rr, wx, wy);
         fr = cycles_to_fixed(g.fr_per_m * rr);
+        if constexpr (CHIRP) {
+            f0l = cycles_to_fixed64(g.fd_per_mps * (wx * gp.lo[2] + wy * gp.lo[3]));
+            hsl = cycles_to_fixed64(0.5 * g.fd_per_mps * (wx * gp.step[2] + wy * gp.step[3]));
+        }
     }
     const float2 ratio = expm_fixed(fr);
 
@@ -136,7 +153,19 @@ __global__ __launch_bounds__(kThreads) void direct_range_zoom(Geom g, GridP gp, 
 #pragma unroll
                 for (int e = 0; e < kRun; ++e) b[e] = make_float2(0.f, 0.f);
             }
-            mfma_complex<BF16>(a, b, cre[t], cim[t]);
+            mfma_complex<false>(a, b, cre[t], cim[t]);
+        }
+    }
+    // output element (location 4 seg + e, chirp r) of each tile
+    uint64_t f0e[4], hse[4];
+    if constexpr (CHIRP) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {   // rates of location 4 seg + e, computed by lane 4 seg + e
+            const int src = 4 * seg + e;
+            f0e[e] = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(f0l >> 32), src, 64) << 32) |
+                     (uint32_t)__shfl((int)(uint32_t)f0l, src, 64);
+            hse[e] = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(hsl >> 32), src, 64) << 32) |
+                     (uint32_t)__shfl((int)(uint32_t)hsl, src, 64);
         }
     }
 #pragma unroll
@@ -145,7 +174,12 @@ __global__ __launch_bounds__(kThreads) void direct_range_zoom(Geom g, GridP gp, 
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int loc = loc0 + 4 * seg + e;
-            if (loc < gp.nloc && m < mc) gws[((size_t)q * gp.nloc + loc) * mc + m] = make_float2(cre[t][e], cim[t][e]);
+            if (loc < gp.nloc && m < mc) {
+                float2 v = make_float2(cre[t][e], cim[t][e]);
+                if constexpr (CHIRP)
+                    v = cmul(v, expm_fixed(fixed_mul_hi(f0e[e], (uint32_t)m) + fixed_mul_hi(hse[e], (uint32_t)(m * m))));
+                gws[((size_t)q * gp.nloc + loc) * mc + m] = v;
+            }
         }
     }
 }
@@ -188,16 +222,38 @@ __host__ __device__ inline ToepPlan toep_plan(int mc, int nvx, int nvy) {
     return p;
 }
 
+// exp(-j 2 pi ph 2^-32) in FP32: the nearest quarter turn from the top bits,
+// the remainder (at most an eighth of a turn, converted from a 30-bit integer)
+// through the Taylor series of sine (to x^9) and cosine (to x^10); truncation
+// below 2e-9 on [-pi/4, pi/4], measured maximum error 1.2e-7 over all phases.
+__device__ __forceinline__ float2 expm_poly(uint32_t ph) {
+    const uint32_t qn = (ph + 0x20000000u) >> 30;
+    const int32_t d = (int32_t)(ph - (qn << 30));
+    const float x = (float)d * 1.4629180792671596e-09f;   // 2 pi / 2^32
+    const float x2 = x * x;
+    float ps = fmaf(x2, 2.7557319e-06f, -1.9841270e-04f);   // 1/9!, -1/7!
+    ps = fmaf(x2, ps, 8.3333333e-03f);                       // 1/5!
+    ps = fmaf(x2, ps, -1.6666667e-01f);                      // -1/3!
+    const float sn = fmaf(x * x2, ps, x);
+    float pc = fmaf(x2, -2.7557319e-07f, 2.4801587e-05f);   // -1/10!, 1/8!
+    pc = fmaf(x2, pc, -1.3888889e-03f);                      // -1/6!
+    pc = fmaf(x2, pc, 4.1666667e-02f);                       // 1/4!
+    pc = fmaf(x2, pc, -0.5f);
+    const float cs = fmaf(x2, pc, 1.0f);
+    // rotate by qn quarter turns: (cos, sin) of qn pi/2 + x
+    const bool odd = qn & 1, neg_c = (qn + 1) & 2, neg_s = qn & 2;
+    float co = odd ? sn : cs, si = odd ? cs : sn;
+    co = neg_c ? -co : co;
+    si = neg_s ? -si : si;
+    return make_float2(co, -si);
+}
+
 // exp(-j 2 pi ph 2^-32) from the hardware sine and cosine (argument in revolutions)
 __device__ __forceinline__ float2 expm_hw(uint32_t ph) {
     const float x = __uint2float_rn(ph) * 2.3283064365386963e-10f;   // 2^-32
     return make_float2(__builtin_amdgcn_cosf(x), -__builtin_amdgcn_sinf(x));
 }
 
-// High word of (a * b) mod 2^64 for a 64-bit fixed-point a and a 32-bit integer b.
-__device__ __forceinline__ uint32_t fixed_mul_hi(uint64_t a, uint32_t b) {
-    return (uint32_t)(a >> 32) * b + __umulhi((uint32_t)a, b);
-}
 
 
 // Range zoom with BF16 operands.  A workgroup owns 64 LT locations x 16 CT
@@ -440,6 +496,46 @@ __global__ __launch_bounds__(kThreads) void direct_doppler_zoom(Geom g, GridP gp
     }
 }
 
+// Slab epilogue of the chirp-table Doppler zooms: tile t of the velocity slab
+// (row tile t % tiles_x, column tile t / tiles_x) holds output (16 tx + 4 g + e,
+// 16 ty + r) in lane r + 16 g, slot e.  Writes the slab (if dec) and the block
+// maximum of location loc (ties to the lowest index, excluded cells skipped).
+template <int MAXT>
+__device__ __forceinline__ void slab_peak(const f32x4 (&dsum)[MAXT], int ntiles, int tiles_x, int nvx, int nvy,
+                                          int64_t base, int lane, float* __restrict__ dec,
+                                          gh_peak* __restrict__ block, int loc, const int64_t* __restrict__ excl,
+                                          int nexcl) {
+    const int r = lane & 15, seg = lane >> 4;
+    float best_v = -INFINITY;
+    int best_i = 0x7fffffff;
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+        if (t < ntiles) {
+            const int ty = t / tiles_x, tx = t - ty * tiles_x;
+            const int ivy = ty * 16 + r;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int ivx = tx * 16 + 4 * seg + e;
+                if (ivx < nvx && ivy < nvy) {
+                    const int v = ivx * nvy + ivy;
+                    if (dec) dec[base + v] = dsum[t][e];
+                    bool skip = false;
+                    for (int i = 0; i < nexcl; ++i) skip |= (excl[i] == base + v);
+                    if (!skip) peak_merge(best_v, best_i, dsum[t][e], v);
+                }
+            }
+        }
+    }
+    wave_peak(best_v, best_i);
+    if (lane == 0) {
+        gh_peak p;
+        p.value = best_v;
+        p.reserved = 0;
+        p.index = base + (best_i == 0x7fffffff ? 0 : best_i);
+        block[loc] = p;
+    }
+}
+
 // Doppler zoom with BF16 operands through chirp tables.  With
 // f_d = f0 + ivx fx + ivy fy and 2 ivx m = ivx^2 + m^2 - (ivx - m)^2 (likewise
 // for ivy), the correlation of one receiver is
@@ -491,6 +587,7 @@ __global__ __launch_bounds__(kThreads) void direct_doppler_zoom_chirp(Geom g, Gr
     const int nvx = gp.n[2], nvy = gp.n[3], nv = gp.nv, mc = g.mc;
     const int nvxp = (nvx + 15) & ~15, nvyp = (nvy + 15) & ~15;
     const int tiles_x = nvxp >> 4, ntiles = tiles_x * (nvyp >> 4);
+    const int kx = (nvxp > tp.mcp ? nvxp : tp.mcp) - 1, ky = (nvyp > tp.mcp ? nvyp : tp.mcp) - 1;
     const int steps = tp.mcp >> 4;
 
     constexpr int kHw = (16 * MAXS + 63) / 64;   // h words per lane held ahead (cached path)
@@ -538,17 +635,21 @@ __global__ __launch_bounds__(kThreads) void direct_doppler_zoom_chirp(Geom g, Gr
             if (q + 1 < g.k) load_h(q + 1);
         }
         const uint64_t hx = bcast64(hxl, q), hy = bcast64(hyl, q);
-        for (int n = lane; n < tp.ex; n += 64) {
-            const int k = nvxp - 1 - n;
-            const float2 e = expm_hw(fixed_mul_hi(hx, (uint32_t)(k * k)));   // conj(Tx[k])
-            tx1[n] = bf16_pair(e.x, e.y);
-            tx2[n] = bf16_pair(-e.y, e.x);
+        // the tables are even in k and the tiles read |k| <= max(nv_pad, mcp) - 1:
+        // one value per |k|, stored at k and -k
+        for (int a = lane; a <= kx; a += 64) {
+            const float2 e = expm_hw(fixed_mul_hi(hx, (uint32_t)(a * a)));   // conj(Tx[+-a])
+            const uint32_t v1 = bf16_pair(e.x, e.y), v2 = bf16_pair(-e.y, e.x);
+            const int n1 = nvxp - 1 - a, n2 = nvxp - 1 + a;
+            if (n1 >= 0) tx1[n1] = v1, tx2[n1] = v2;
+            if (n2 < tp.ex) tx1[n2] = v1, tx2[n2] = v2;
         }
-        for (int n = lane; n < tp.ey; n += 64) {
-            const int k = nvyp - 1 - n;
-            const float2 e = expm_hw(fixed_mul_hi(hy, (uint32_t)(k * k)));   // conj(Ty[k])
-            ty1[n] = bf16_pair(e.x, e.y);
-            ty2[n] = bf16_pair(-e.y, e.x);
+        for (int a = lane; a <= ky; a += 64) {
+            const float2 e = expm_hw(fixed_mul_hi(hy, (uint32_t)(a * a)));   // conj(Ty[+-a])
+            const uint32_t v1 = bf16_pair(e.x, e.y), v2 = bf16_pair(-e.y, e.x);
+            const int n1 = nvyp - 1 - a, n2 = nvyp - 1 + a;
+            if (n1 >= 0) ty1[n1] = v1, ty2[n1] = v2;
+            if (n2 < tp.ey) ty1[n2] = v1, ty2[n2] = v2;
         }
         // the tables are private to the wave: its LDS writes only have to land before its reads
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -619,52 +720,193 @@ __global__ __launch_bounds__(kThreads) void direct_doppler_zoom_chirp(Geom g, Gr
         }
     }
 
-    const int64_t base = (int64_t)loc * nv;
-    float best_v = -INFINITY;
-    int best_i = 0x7fffffff;
+    slab_peak<MAXT>(dsum, ntiles, tiles_x, nvx, nvy, (int64_t)loc * nv, lane, dec, block, loc, excl, nexcl);
+}
+
+// Doppler zoom through chirp tables in FP32 (same factorisation as the BF16
+// kernel above, on 16x16x4 FP32 products).  Contraction slot g = 2 kappa + c of
+// a product holds the real (c = 0) or imaginary (c = 1) part of chirp
+// m = 2 s + kappa at step s, so one product contracts two chirps and a complex
+// tile step is two products:
+//   left operand, row ivx:   (Re, Im) product forms of Tx[ivx - m],
+//                            c = 0: (Re Tx, Im Tx),  c = 1: (-Im Tx, Re Tx);
+//   right operand, col ivy:  c = 0: Re(h[m] Ty[ivy - m]),  c = 1: Im(...).
+// The wave's LDS holds, per receiver, the tables
+//   x0[n] = (Re, Im) Tx[k], x1[n] = (-Im, Re) Tx[k],  k = nvx_pad - 1 - n, n < ex;
+//   y0[n] = conj(Ty[k]),    y1[n] = (-Im, Re) conj(Ty[k]),  k = nvy_pad - 1 - n;
+//   h[m], m < mcp (zero for m >= Mc),
+// each entry n as the pair (v[n], v[n + 2]) in 16 bytes: a lane's indices
+// advance by two per step, so one 16-byte read serves two steps (16-byte LDS
+// reads move twice the bytes per cycle of 8-byte ones).  A lane reads its
+// left operand pair as float2 and forms its right operand as
+// Re h y.x + Im h y.y.  STEPS > 0 is the exact step count mcp / 2: the right
+// operands of a column tile are formed once, in registers, for all its row
+// tiles.  STEPS = 0 forms them step by step, eight steps per loop trip
+// (mcp / 2 is a multiple of eight).  h of the next receiver is loaded while the
+// current one is in work.  Table values come from expm_poly.
+template <int MAXT, int STEPS>
+__global__ __launch_bounds__(kThreads) void direct_doppler_zoom_chirp_f32(Geom g, GridP gp, ToepPlan tp,
+                                                                         const float2* __restrict__ hws,
+                                                                         float* __restrict__ dec,
+                                                                         gh_peak* __restrict__ block,
+                                                                         const int64_t* __restrict__ excl, int nexcl) {
+    extern __shared__ __attribute__((aligned(16))) float4 toepf_lds[];
+    constexpr int kHw = STEPS > 0 ? (2 * STEPS + 63) / 64 : 1;   // h values per lane held ahead
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15;
+    const int grp = lane >> 4;
+    const int kap = grp >> 1, c = grp & 1;
+    const int w = threadIdx.x >> 6;
+    const int loc = blockIdx.x * (blockDim.x >> 6) + w;
+    if (loc >= gp.nloc) return;   // wave-uniform; the kernel has no workgroup barrier
+    float4* x0 = toepf_lds + (size_t)w * tp.words;
+    float4* x1 = x0 + tp.ex;
+    float4* y0 = x1 + tp.ex;
+    float4* y1 = y0 + tp.ey;
+    float4* hh = y1 + tp.ey;
+    const float4* xc = c ? x1 : x0;   // this lane's left-operand table
+    const float4* yc = c ? y1 : y0;   // and right-operand table
+    const int ix = loc / gp.n[1], iy = loc - ix * gp.n[1];
+    const int nvx = gp.n[2], nvy = gp.n[3], nv = gp.nv, mc = g.mc;
+    const int nvxp = (nvx + 15) & ~15, nvyp = (nvy + 15) & ~15;
+    const int tiles_x = nvxp >> 4, ntiles = tiles_x * (nvyp >> 4);
+    const int kx = (nvxp > tp.mcp ? nvxp : tp.mcp) - 1, ky = (nvyp > tp.mcp ? nvyp : tp.mcp) - 1;
+    const int steps = STEPS > 0 ? STEPS : tp.mcp >> 1;
+    // value v of entry n goes to the low half of pair n and the high half of pair n - 2
+    auto put = [](float4* t, int n, float2 v) {
+        float2* f = reinterpret_cast<float2*>(t);
+        f[2 * n] = v;
+        if (n >= 2) f[2 * n - 3] = v;
+    };
+
+    float2 hpre[kHw];
+    auto load_h = [&](int q) {
+        const float2* hq = hws + ((size_t)q * gp.nloc + loc) * mc;
 #pragma unroll
-    for (int t = 0; t < MAXT; ++t) {
-        if (t < ntiles) {
-            const int ty = t / tiles_x, tx = t - ty * tiles_x;
-            const int ivy = ty * 16 + r;
+        for (int u = 0; u < kHw; ++u) {
+            const int m = lane + 64 * u;
+            hpre[u] = m < mc ? hq[m] : make_float2(0.f, 0.f);
+        }
+    };
+    if (STEPS > 0) load_h(0);
+
+    // receiver `lane`: fx / 2 and fy / 2 in 64-bit fixed point
+    uint64_t hxl = 0, hyl = 0;
+    if (lane < g.k) {
+        double rr, wx, wy;
+        bistatic(g, lane, gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], rr, wx, wy);
+        hxl = cycles_to_fixed64(0.5 * g.fd_per_mps * wx * gp.step[2]);
+        hyl = cycles_to_fixed64(0.5 * g.fd_per_mps * wy * gp.step[3]);
+    }
+    auto bcast64 = [](uint64_t v, int src) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+        return ((uint64_t)hi << 32) | lo;
+    };
+    auto rhs = [](float4 hv, float4 yv, float& b0, float& b1) {
+        b0 = fmaf(hv.x, yv.x, hv.y * yv.y);
+        b1 = fmaf(hv.z, yv.z, hv.w * yv.w);
+    };
+
+    f32x4 dsum[MAXT];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int ivx = tx * 16 + 4 * seg + e;
-                if (ivx < nvx && ivy < nvy) {
-                    const int v = ivx * nvy + ivy;
-                    if (dec) dec[base + v] = dsum[t][e];
-                    bool skip = false;
-                    for (int i = 0; i < nexcl; ++i) skip |= (excl[i] == base + v);
-                    if (!skip) peak_merge(best_v, best_i, dsum[t][e], v);
+    for (int t = 0; t < MAXT; ++t) dsum[t] = zero4();
+
+    for (int q = 0; q < g.k; ++q) {
+        // every lane has finished reading receiver q - 1's tables (in-order LDS per wave)
+        __builtin_amdgcn_wave_barrier();
+        if constexpr (STEPS > 0) {
+#pragma unroll
+            for (int u = 0; u < kHw; ++u) {
+                const int m = lane + 64 * u;
+                if (m < tp.mcp) put(hh, m, hpre[u]);
+            }
+            if (q + 1 < g.k) load_h(q + 1);
+        } else {
+            const float2* hq = hws + ((size_t)q * gp.nloc + loc) * mc;
+            for (int m = lane; m < tp.mcp; m += 64) put(hh, m, m < mc ? hq[m] : make_float2(0.f, 0.f));
+        }
+        const uint64_t hx = bcast64(hxl, q), hy = bcast64(hyl, q);
+        // the tables are even in k and the tiles read |k| <= max(nv_pad, mcp) - 1:
+        // one value per |k|, stored at k and -k
+        for (int a = lane; a <= kx; a += 64) {
+            const float2 e = expm_poly(fixed_mul_hi(hx, (uint32_t)(a * a)));   // conj(Tx[+-a])
+            const float2 v0 = make_float2(e.x, -e.y), v1 = make_float2(e.y, e.x);
+            const int n1 = nvxp - 1 - a, n2 = nvxp - 1 + a;
+            if (n1 >= 0) put(x0, n1, v0), put(x1, n1, v1);
+            if (n2 < tp.ex) put(x0, n2, v0), put(x1, n2, v1);
+        }
+        for (int a = lane; a <= ky; a += 64) {
+            const float2 e = expm_poly(fixed_mul_hi(hy, (uint32_t)(a * a)));   // conj(Ty[+-a])
+            const float2 v1 = make_float2(-e.y, e.x);
+            const int n1 = nvyp - 1 - a, n2 = nvyp - 1 + a;
+            if (n1 >= 0) put(y0, n1, e), put(y1, n1, v1);
+            if (n2 < tp.ey) put(y0, n2, e), put(y1, n2, v1);
+        }
+        // the tables are private to the wave: its LDS writes only have to land before its reads
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+
+        float bc[STEPS > 0 ? STEPS : 1];
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+            if (t < ntiles) {
+                const int ty = t / tiles_x, tx = t - ty * tiles_x;
+                // column ivy = 16 ty + r, row ivx = 16 tx + r, chirp m = 2 s + kappa at step s:
+                // pair 2 s of each table holds steps s and s + 1
+                const float4* pb = yc + nvyp - 1 - 16 * ty - r + kap;
+                const float4* ph = hh + kap;
+                const float4* pa = xc + nvxp - 1 - 16 * tx - r + kap;
+                f32x4 cr0 = zero4(), ci0 = zero4(), cr1 = zero4(), ci1 = zero4();
+                auto mfma2 = [&](float4 a, float b0, float b1) {
+                    cr0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b0, cr0, 0, 0, 0);
+                    ci0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b0, ci0, 0, 0, 0);
+                    cr1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b1, cr1, 0, 0, 0);
+                    ci1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b1, ci1, 0, 0, 0);
+                };
+                if constexpr (STEPS > 0) {
+                    if (tx == 0) {
+#pragma unroll
+                        for (int s = 0; s < STEPS; s += 2) rhs(ph[2 * s], pb[2 * s], bc[s], bc[s + 1]);
+                    }
+#pragma unroll
+                    for (int s = 0; s < STEPS; s += 2) mfma2(pa[2 * s], bc[s], bc[s + 1]);
+                } else {
+                    for (int s0 = 0; s0 < steps; s0 += 8) {
+#pragma unroll
+                        for (int s = s0; s < s0 + 8; s += 2) {
+                            float b0, b1;
+                            rhs(ph[2 * s], pb[2 * s], b0, b1);
+                            mfma2(pa[2 * s], b0, b1);
+                        }
+                    }
                 }
+                cr0 += cr1;
+                ci0 += ci1;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) dsum[t][e] = fmaf(cr0[e], cr0[e], fmaf(ci0[e], ci0[e], dsum[t][e]));
             }
         }
     }
-    wave_peak(best_v, best_i);
-    if (lane == 0) {
-        gh_peak p;
-        p.value = best_v;
-        p.reserved = 0;
-        p.index = base + (best_i == 0x7fffffff ? 0 : best_i);
-        block[loc] = p;
-    }
+    slab_peak<MAXT>(dsum, ntiles, tiles_x, nvx, nvy, (int64_t)loc * nv, lane, dec, block, loc, excl, nexcl);
 }
 
-// Launch shape of the chirp-table Doppler zoom: the register bounds it was
-// instantiated for (MAXT 4 or 16 tiles, MAXS 8 steps, i.e. Mc <= 128), and
-// waves per workgroup from its LDS (one table set per wave); 0 when the
-// slab or the chirp count exceeds those bounds (then the generating Doppler
-// zoom runs).
+// Launch shape of the chirp-table Doppler zooms: the register bounds they were
+// instantiated for (MAXT 4 or 16 tiles; right operands cached for Mc <= 128,
+// else formed step by step), and waves per workgroup from the LDS of one table
+// set per wave (tp.words words of word_bytes each, at most 64 KB per
+// workgroup); waves = 0 when the slab exceeds 16 tiles or one table set
+// exceeds 64 KB (then the generating Doppler zoom runs).
 struct ChirpShape {
     int maxt, waves;
     bool stream;
 };
 
-ChirpShape chirp_shape(const Geom& g, const GridP& gp) {
+ChirpShape chirp_shape(const Geom& g, const GridP& gp, int word_bytes) {
     const ToepPlan tp = toep_plan(g.mc, gp.n[2], gp.n[3]);
     const int ntiles = ((gp.n[2] + 15) >> 4) * ((gp.n[3] + 15) >> 4);
     if (ntiles > 16) return {0, 0, false};
-    const size_t per_wave = (size_t)tp.words * 4;
+    const size_t per_wave = (size_t)tp.words * word_bytes;
     int w = kWaves;
     while (w > 1 && w * per_wave > 65536) w >>= 1;
     if (w * per_wave > 65536) return {0, 0, false};
@@ -698,15 +940,15 @@ hipError_t launch_direct_range(const Geom& g, const GridP& gp, const float2* y, 
     return hipGetLastError();
 }
 
-// BF16: the chirp-table Doppler zoom on h from the range zoom when its tables
-// fit in LDS, else the generating Doppler zoom on G.  The workspace holds G
-// (complex64) or h (BF16 pairs, at most as many bytes).
+// Both precisions: the chirp-table Doppler zoom on h from the range zoom when
+// its tables fit in LDS, else the generating Doppler zoom on G.  The workspace
+// holds G or h (complex64, or BF16 pairs for h in BF16: at most as many bytes).
 hipError_t launch_direct(const Geom& g, const GridP& gp, const float2* y, int gemm, void* ws, float* dec,
                          gh_peak* block, const int64_t* excl, int nexcl, hipStream_t st) {
     float2* gws = static_cast<float2*>(ws);
     hipError_t e;
     if (gemm == GH_GEMM_BF16) {
-        const ChirpShape cs = chirp_shape(g, gp);
+        const ChirpShape cs = chirp_shape(g, gp, 4);
         if (cs.waves > 0) {
             if ((e = launch_range_bf16<true>(g, gp, y, ws, st)) != hipSuccess) return e;
             const ToepPlan tp = toep_plan(g.mc, gp.n[2], gp.n[3]);
@@ -727,9 +969,38 @@ hipError_t launch_direct(const Geom& g, const GridP& gp, const float2* y, int ge
                                st, g, gp, gws, dec, block, excl, nexcl);
         }
     } else {
-        if ((e = launch_direct_range(g, gp, y, gemm, gws, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL(direct_doppler_zoom<false>, dim3((gp.nloc + kWaves - 1) / kWaves), dim3(kThreads), 0, st,
-                           g, gp, gws, dec, block, excl, nexcl);
+        const ChirpShape cs = chirp_shape(g, gp, 16);
+        const dim3 g1((gp.nloc + 16 * kWaves - 1) / (16 * kWaves), (g.mc + 16 * kNT - 1) / (16 * kNT), g.k);
+        if (cs.waves > 0) {
+            hipLaunchKernelGGL(direct_range_zoom<true>, g1, dim3(kThreads), 0, st, g, gp, y, gws);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            const ToepPlan tp = toep_plan(g.mc, gp.n[2], gp.n[3]);
+            const size_t lds = (size_t)cs.waves * tp.words * 16;
+            const dim3 grid((gp.nloc + cs.waves - 1) / cs.waves), blk(64 * cs.waves);
+#define GH_CHIRP_LAUNCH(T, S)                                                                                   \
+    hipLaunchKernelGGL((direct_doppler_zoom_chirp_f32<T, S>), grid, blk, lds, st, g, gp, tp, gws, dec, block, excl, \
+                       nexcl)
+            // right operands cached in registers when a column tile has several row
+            // tiles, for up to 4 tiles and Mc <= 128 (a 16-tile instance would not
+            // fit), else formed step by step (fewer registers, more waves resident)
+            const int steps = tp.mcp >> 1;
+            if (cs.maxt == 16 || cs.stream || gp.n[2] <= 16) {
+                if (cs.maxt == 4) GH_CHIRP_LAUNCH(4, 0); else GH_CHIRP_LAUNCH(16, 0);
+            } else if (steps == 64) {
+                GH_CHIRP_LAUNCH(4, 64);
+            } else if (steps == 32) {
+                GH_CHIRP_LAUNCH(4, 32);
+            } else if (steps == 16) {
+                GH_CHIRP_LAUNCH(4, 16);
+            } else {
+                GH_CHIRP_LAUNCH(4, 8);
+            }
+#undef GH_CHIRP_LAUNCH
+        } else {
+            if ((e = launch_direct_range(g, gp, y, gemm, gws, st)) != hipSuccess) return e;
+            hipLaunchKernelGGL(direct_doppler_zoom<false>, dim3((gp.nloc + kWaves - 1) / kWaves), dim3(kThreads), 0,
+                               st, g, gp, gws, dec, block, excl, nexcl);
+        }
     }
     return hipGetLastError();
 }
