@@ -23,9 +23,11 @@
 //     P_d >= 2).
 // LDS sequences are padded to an odd stride so the transposed reads of the
 // store phase do not conflict.  For single frames whose transforms fit one
-// wave (Ms <= 512, P_d Mc <= 512), each wave owns one chirp (pass 1) or one
-// row (pass 2) and runs its stages without workgroup barriers (range_pass_w,
-// doppler_pass_w); batches and larger frames use the workgroup-wide passes.
+// wave (Ms <= 512, P_d Mc <= 512, or twice that with P_d >= 2), each wave
+// owns one chirp (pass 1) or one row, or half of a row's P_d sub-transforms
+// when P_d >= 2 (pass 2), and runs its stages without workgroup barriers
+// (range_pass_w, doppler_pass_w); batches and larger frames use the
+// workgroup-wide passes.
 #include "gh_internal.h"
 
 namespace gh {
@@ -367,10 +369,15 @@ __global__ __launch_bounds__(kThreads) void range_pass_w(Geom g, size_t row_byte
     }
 }
 
-// Doppler pass: a workgroup of W waves owns range rows i0 .. i0 + W - 1 of
-// receiver q, one row (its P sub-transforms) per wave; the only workgroup
-// barrier is the table build's.  Each wave overwrites its own row.
-template <int DT, int NP>
+// Doppler pass: a workgroup of W waves owns range rows i0 .. i0 + W / S - 1
+// of receiver q, S waves per row, each with P / S of the row's P
+// sub-transforms (S = 1 or 2).  S = 1: the only workgroup barrier is the
+// table build's, and each wave overwrites its own row.  S = 2: the two waves
+// of a row meet at a second workgroup barrier, after which each writes half
+// of the row's bins (the barrier also orders both waves' reads of the parked
+// spectra before either overwrites them).  Splitting halves each wave's chain
+// of FFT stages and doubles the resident waves.
+template <int DT, int NP, int S>
 __global__ __launch_bounds__(kThreads) void doppler_pass_w(Geom g, char* __restrict__ maps,
                                                           unsigned* __restrict__ clear) {
     extern __shared__ float2 lds[];
@@ -378,9 +385,11 @@ __global__ __launch_bounds__(kThreads) void doppler_pass_w(Geom g, char* __restr
     const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int mc = g.mc, pd = g.pd, nd = g.nd, stride = mc + 1;
     const int log2pd = __ffs(pd) - 1;
-    const int q = blockIdx.y, row_i = blockIdx.x * nw + w;
-    float2* buf = lds;                        // [nw][pd][mc + 1]
-    float2* tw = buf + nw * pd * stride;      // [mc]
+    const int wr = w / S, half = w - wr * S;  // the wave's row in the workgroup, and its part
+    const int q = blockIdx.y, row_i = blockIdx.x * (nw / S) + wr;
+    const int np = pd / S, p0 = half * np;   // the wave's sub-transforms
+    float2* buf = lds;                        // [nw / S][pd][mc + 1]
+    float2* tw = buf + (nw / S) * pd * stride;   // [mc]
     float2* cen = tw + mc;                    // [mc]
     float2* pre = cen + mc;                   // [pd][mc]
     constexpr int kEs = map_elem_bytes(DT);
@@ -394,19 +403,21 @@ __global__ __launch_bounds__(kThreads) void doppler_pass_w(Geom g, char* __restr
     }
     fill_tables(pre, tw, cen, 0, mc, nd, g.centered, true, pd);
     __syncthreads();
-    float2* bw = buf + w * pd * stride;
+    float2* bw = buf + wr * pd * stride;
 #pragma unroll
     for (int j = 0; j < NP / 64; ++j) {
         const int m = lane + 64 * j;
         if (m < mc)
-            for (int p = 0; p < pd; ++p) bw[p * stride + m] = cmulf(x[j], pre[p * mc + m]);
+            for (int p = p0; p < p0 + np; ++p) bw[p * stride + m] = cmulf(x[j], pre[p * mc + m]);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    wave_fft<NP>(bw, pd, stride, g.log2_mc, tw);
-    // out bin l = P k + p, bins fastest
+    wave_fft<NP>(bw + p0 * stride, np, stride, g.log2_mc, tw);
+    if constexpr (S > 1) __syncthreads();
+    // out bin l = P k + p, bins fastest; part `half` writes bins [half nd / S, (half + 1) nd / S)
     const float inv_scale = 1.f / map_scale(g.ms, mc, DT);
-    for (int l = lane; l < nd; l += 64) {
+    const int l_end = (half + 1) * (nd / S);
+    for (int l = half * (nd / S) + lane; l < l_end; l += 64) {
         const int k = l >> log2pd, p = l & (pd - 1);
         const float2 v = cmulf(bw[p * stride + k], cen[k]);
         if constexpr (DT == GH_MAP_C64) {
@@ -430,12 +441,19 @@ int range_waves(const Geom& g) {
     return 0;
 }
 
+// Doppler: waves per row S = 2 when the row has an even number of
+// sub-transforms, else 1; W / S rows per workgroup.
+int doppler_split(const Geom& g) { return g.pd >= 2 ? 2 : 1; }
+
+size_t doppler_w_lds(const Geom& g, int w) {
+    return ((size_t)(w / doppler_split(g)) * g.pd * (g.mc + 1) + (2 + (size_t)g.pd) * g.mc) * sizeof(float2);
+}
+
 int doppler_waves(const Geom& g) {
-    if ((long)g.pd * g.mc > kWavePts) return 0;
-    for (int w = 8; w >= 2; w >>= 1) {
-        const size_t lds = ((size_t)w * g.pd * (g.mc + 1) + (2 + (size_t)g.pd) * g.mc) * sizeof(float2);
-        if (lds <= 65536 && g.nr % w == 0) return w;
-    }
+    const int sp = doppler_split(g);
+    if ((long)g.pd * g.mc / sp > kWavePts) return 0;
+    for (int w = 8; w >= 2; w >>= 1)
+        if (doppler_w_lds(g, w) <= 65536 && g.nr % (w / sp) == 0) return w;
     return 0;
 }
 
@@ -587,15 +605,20 @@ hipError_t launch_rd_maps(const Geom& g, const float2* y, void* maps_v, int map_
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (w2 > 0) {
-        const size_t l = ((size_t)w2 * g.pd * (g.mc + 1) + (2 + (size_t)g.pd) * g.mc) * sizeof(float2);
-        const dim3 grid(g.nr / w2, g.k), blk(64 * w2);
-        const int pts = g.pd * g.mc;
+        const int sp = doppler_split(g);
+        const size_t l = doppler_w_lds(g, w2);
+        const dim3 grid(g.nr / (w2 / sp), g.k), blk(64 * w2);
+        const int pts = g.pd * g.mc / sp;   // points per wave
 #define GH_DOPPLER_W(DT)                                                                            \
     do {                                                                                            \
-        if (pts <= 256)                                                                             \
-            hipLaunchKernelGGL((doppler_pass_w<DT, 256>), grid, blk, l, st, g, maps, clear);        \
+        if (sp == 1 && pts <= 256)                                                                  \
+            hipLaunchKernelGGL((doppler_pass_w<DT, 256, 1>), grid, blk, l, st, g, maps, clear);     \
+        else if (sp == 1)                                                                           \
+            hipLaunchKernelGGL((doppler_pass_w<DT, 512, 1>), grid, blk, l, st, g, maps, clear);     \
+        else if (pts <= 256)                                                                        \
+            hipLaunchKernelGGL((doppler_pass_w<DT, 256, 2>), grid, blk, l, st, g, maps, clear);     \
         else                                                                                        \
-            hipLaunchKernelGGL((doppler_pass_w<DT, 512>), grid, blk, l, st, g, maps, clear);        \
+            hipLaunchKernelGGL((doppler_pass_w<DT, 512, 2>), grid, blk, l, st, g, maps, clear);     \
     } while (0)
         if (map_dtype == GH_MAP_F16)
             GH_DOPPLER_W(GH_MAP_F16);

@@ -73,7 +73,8 @@ def test_rd_maps_parity(cfg, centered):
 
 
 @pytest.mark.parametrize("ms,mc,pad_r,pad_d,k", [(8, 8, 1, 1, 1), (16, 64, 8, 2, 2), (128, 8, 2, 8, 3),
-                                                 (1024, 8, 4, 1, 1), (8, 1024, 1, 4, 1), (32, 16, 8, 8, 16)])
+                                                 (1024, 8, 4, 1, 1), (8, 1024, 1, 4, 1), (32, 16, 8, 8, 16),
+                                                 (64, 256, 2, 4, 2)])
 def test_rd_maps_shapes(ms, mc, pad_r, pad_d, k):
     say(f"rd_maps shapes ms={ms} mc={mc} pads={pad_r},{pad_d} k={k}")
     rng = np.random.default_rng(ms * 7 + mc)
