@@ -97,13 +97,9 @@ __device__ __forceinline__ void load_run(const float2* __restrict__ p, float2 (&
     }
 }
 
-// Range zoom (FP32).  Grid (ceil(Nloc / 64), ceil(Mc / 64), K); wave w of a
-// workgroup owns 16 locations and 64 chirps of receiver blockIdx.z.
-//   CHIRP = false: G_q[x][m] (complex64 [K][Nloc][Mc]);
-//   CHIRP = true:  h_q[x][m] = G_q[x][m] exp(-j 2 pi (f0 m + (fx + fy) m^2 / 2))
-//                  (complex64 [K][Nloc][Mc]), the right-hand factor of the
-//                  chirp-table Doppler zoom below.
-template <bool CHIRP>
+// Range zoom (FP32), G_q[x][m] (complex64 [K][Nloc][Mc]).  Grid
+// (ceil(Nloc / 64), ceil(Mc / 64), K); wave w of a workgroup owns 16
+// locations and 64 chirps of receiver blockIdx.z.
 __global__ __launch_bounds__(kThreads) void direct_range_zoom(Geom g, GridP gp, const float2* __restrict__ y,
                                                              float2* __restrict__ gws) {
     const int lane = threadIdx.x & 63;
@@ -115,17 +111,12 @@ __global__ __launch_bounds__(kThreads) void direct_range_zoom(Geom g, GridP gp, 
     const int ms = g.ms, mc = g.mc;
 
     uint32_t fr = 0;
-    uint64_t f0l = 0, hsl = 0;
     if (loc0 + r < gp.nloc) {
         const int loc = loc0 + r;
         const int ix = loc / gp.n[1], iy = loc - ix * gp.n[1];
         double rr, wx, wy;
         bistatic(g, q, gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], rr, wx, wy);
         fr = cycles_to_fixed(g.fr_per_m * rr);
-        if constexpr (CHIRP) {
-            f0l = cycles_to_fixed64(g.fd_per_mps * (wx * gp.lo[2] + wy * gp.lo[3]));
-            hsl = cycles_to_fixed64(0.5 * g.fd_per_mps * (wx * gp.step[2] + wy * gp.step[3]));
-        }
     }
     const float2 ratio = expm_fixed(fr);
 
@@ -157,28 +148,113 @@ __global__ __launch_bounds__(kThreads) void direct_range_zoom(Geom g, GridP gp, 
         }
     }
     // output element (location 4 seg + e, chirp r) of each tile
-    uint64_t f0e[4], hse[4];
-    if constexpr (CHIRP) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {   // rates of location 4 seg + e, computed by lane 4 seg + e
-            const int src = 4 * seg + e;
-            f0e[e] = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(f0l >> 32), src, 64) << 32) |
-                     (uint32_t)__shfl((int)(uint32_t)f0l, src, 64);
-            hse[e] = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(hsl >> 32), src, 64) << 32) |
-                     (uint32_t)__shfl((int)(uint32_t)hsl, src, 64);
-        }
-    }
 #pragma unroll
     for (int t = 0; t < kNT; ++t) {
         const int m = m0 + t * 16 + r;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int loc = loc0 + 4 * seg + e;
+            if (loc < gp.nloc && m < mc) gws[((size_t)q * gp.nloc + loc) * mc + m] = make_float2(cre[t][e], cim[t][e]);
+        }
+    }
+}
+
+// Range zoom (FP32) for the chirp-table Doppler zoom:
+//   h_q[x][m] = G_q[x][m] exp(-j 2 pi (f0 m + (fx + fy) m^2 / 2))   (complex64 [K][Nloc][Mc]).
+// The samples are split over the waves of a workgroup: with nsplit parts
+// (4 for Ms >= 128, 2 for Ms = 64, else 1), the workgroup owns 4 / nsplit
+// tiles of 16 locations x 64 chirps of receiver blockIdx.z, and wave
+// (tile, part) sums samples [part Ms / nsplit, (part + 1) Ms / nsplit).  The
+// partial sums meet in LDS and are added in part order; the wave of part p
+// finishes the chirp tiles p, p + nsplit, ... (chirp factor and store).
+// Grid (ceil(Nloc / (64 / nsplit)), ceil(Mc / 64), K).  Four times the waves
+// of the unsplit kernel at equal work: it shares the device better with the
+// refinement that runs beside it in a step.
+__global__ __launch_bounds__(kThreads) void direct_range_zoom_chirp(Geom g, GridP gp, const float2* __restrict__ y,
+                                                                   float2* __restrict__ hws, int nsplit) {
+    __shared__ f32x4 part[kWaves][2 * kNT][64];
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15;
+    const int seg = lane >> 4;
+    const int w = threadIdx.x >> 6;
+    const int lg = w / nsplit, sp = w - lg * nsplit;   // location tile in the workgroup, sample part
+    const int q = blockIdx.z;
+    const int loc0 = (blockIdx.x * (kWaves / nsplit) + lg) * 16;
+    const int m0 = blockIdx.y * (16 * kNT);
+    const int ms = g.ms, mc = g.mc;
+    const int s_begin = sp * (ms / nsplit), s_end = s_begin + ms / nsplit;
+
+    uint32_t fr = 0;
+    uint64_t f0l = 0, hsl = 0;
+    if (loc0 + r < gp.nloc) {
+        const int loc = loc0 + r;
+        const int ix = loc / gp.n[1], iy = loc - ix * gp.n[1];
+        double rr, wx, wy;
+        bistatic(g, q, gp.lo[0] + ix * gp.step[0], gp.lo[1] + iy * gp.step[1], rr, wx, wy);
+        fr = cycles_to_fixed(g.fr_per_m * rr);
+        f0l = cycles_to_fixed64(g.fd_per_mps * (wx * gp.lo[2] + wy * gp.lo[3]));
+        hsl = cycles_to_fixed64(0.5 * g.fd_per_mps * (wx * gp.step[2] + wy * gp.step[3]));
+    }
+    const float2 ratio = expm_fixed(fr);
+
+    f32x4 cre[kNT], cim[kNT];
+#pragma unroll
+    for (int t = 0; t < kNT; ++t) cre[t] = cim[t] = zero4();
+
+    const float2* yq = y + (size_t)q * mc * ms;
+    for (int s0 = s_begin; s0 < s_end; s0 += 32) {
+        const int sb = s0 + seg * kRun;
+        const bool live = sb < s_end;   // a part is a multiple of 32 samples, or all of Ms (a power of two >= 8)
+        float2 a[kRun];
+        atom_run(fr, (uint32_t)sb, ratio, a);
+        if (!live) {
+#pragma unroll
+            for (int e = 0; e < kRun; ++e) a[e] = make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) {
+            const int m = m0 + t * 16 + r;
+            float2 b[kRun];
+            if (live && m < mc) {
+                load_run(yq + (size_t)m * ms + sb, b);
+            } else {
+#pragma unroll
+                for (int e = 0; e < kRun; ++e) b[e] = make_float2(0.f, 0.f);
+            }
+            mfma_complex<false>(a, b, cre[t], cim[t]);
+        }
+    }
+    // output element (location 4 seg + e, chirp r) of each tile; the chirp
+    // rates of location 4 seg + e come from lane 4 seg + e
+    uint64_t f0e[4], hse[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int src = 4 * seg + e;
+        f0e[e] = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(f0l >> 32), src, 64) << 32) |
+                 (uint32_t)__shfl((int)(uint32_t)f0l, src, 64);
+        hse[e] = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(hsl >> 32), src, 64) << 32) |
+                 (uint32_t)__shfl((int)(uint32_t)hsl, src, 64);
+    }
+#pragma unroll
+    for (int t = 0; t < kNT; ++t) {
+        part[w][2 * t][lane] = cre[t];
+        part[w][2 * t + 1][lane] = cim[t];
+    }
+    __syncthreads();
+    const int w0 = lg * nsplit;
+    for (int t = sp; t < kNT; t += nsplit) {
+        f32x4 sr = part[w0][2 * t][lane], si = part[w0][2 * t + 1][lane];
+        for (int p = 1; p < nsplit; ++p) {
+            sr += part[w0 + p][2 * t][lane];
+            si += part[w0 + p][2 * t + 1][lane];
+        }
+        const int m = m0 + t * 16 + r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int loc = loc0 + 4 * seg + e;
             if (loc < gp.nloc && m < mc) {
-                float2 v = make_float2(cre[t][e], cim[t][e]);
-                if constexpr (CHIRP)
-                    v = cmul(v, expm_fixed(fixed_mul_hi(f0e[e], (uint32_t)m) + fixed_mul_hi(hse[e], (uint32_t)(m * m))));
-                gws[((size_t)q * gp.nloc + loc) * mc + m] = v;
+                const uint32_t ph = fixed_mul_hi(f0e[e], (uint32_t)m) + fixed_mul_hi(hse[e], (uint32_t)(m * m));
+                hws[((size_t)q * gp.nloc + loc) * mc + m] = cmul(make_float2(sr[e], si[e]), expm_fixed(ph));
             }
         }
     }
@@ -936,7 +1012,7 @@ hipError_t launch_range_bf16(const Geom& g, const GridP& gp, const float2* y, vo
 hipError_t launch_direct_range(const Geom& g, const GridP& gp, const float2* y, int gemm, float2* G, hipStream_t st) {
     if (gemm == GH_GEMM_BF16) return launch_range_bf16<false>(g, gp, y, G, st);
     const dim3 g1((gp.nloc + 16 * kWaves - 1) / (16 * kWaves), (g.mc + 16 * kNT - 1) / (16 * kNT), g.k);
-    hipLaunchKernelGGL(direct_range_zoom<false>, g1, dim3(kThreads), 0, st, g, gp, y, G);
+    hipLaunchKernelGGL(direct_range_zoom, g1, dim3(kThreads), 0, st, g, gp, y, G);
     return hipGetLastError();
 }
 
@@ -970,9 +1046,11 @@ hipError_t launch_direct(const Geom& g, const GridP& gp, const float2* y, int ge
         }
     } else {
         const ChirpShape cs = chirp_shape(g, gp, 16);
-        const dim3 g1((gp.nloc + 16 * kWaves - 1) / (16 * kWaves), (g.mc + 16 * kNT - 1) / (16 * kNT), g.k);
         if (cs.waves > 0) {
-            hipLaunchKernelGGL(direct_range_zoom<true>, g1, dim3(kThreads), 0, st, g, gp, y, gws);
+            const int nsplit = g.ms >= 128 ? 4 : (g.ms >= 64 ? 2 : 1);
+            const int tile_locs = 16 * (kWaves / nsplit);
+            const dim3 g1((gp.nloc + tile_locs - 1) / tile_locs, (g.mc + 16 * kNT - 1) / (16 * kNT), g.k);
+            hipLaunchKernelGGL(direct_range_zoom_chirp, g1, dim3(kThreads), 0, st, g, gp, y, gws, nsplit);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             const ToepPlan tp = toep_plan(g.mc, gp.n[2], gp.n[3]);
             const size_t lds = (size_t)cs.waves * tp.words * 16;
