@@ -254,12 +254,14 @@ def test_direct_full_volume_cfg1(gemm, tol):
 
 @pytest.mark.parametrize("ms,mc,n", [(8, 8, (3, 5, 7, 9)), (16, 64, (9, 8, 16, 16)), (64, 32, (5, 13, 17, 33)),
                                      (128, 16, (2, 3, 40, 1)), (32, 128, (1, 1, 1, 1)), (256, 8, (4, 4, 2, 48)),
-                                     (16, 256, (3, 4, 9, 20)), (16, 16, (2, 3, 100, 33))])
+                                     (16, 256, (3, 4, 9, 20)), (16, 16, (2, 3, 100, 33)),
+                                     (32, 128, (3, 4, 20, 10)), (16, 64, (2, 5, 33, 7)), (16, 32, (2, 3, 24, 20))])
 @pytest.mark.parametrize("gemm,tol", GEMMS)
 def test_direct_shapes(ms, mc, n, gemm, tol):
-    """Short contractions (Ms, Mc < 32), ragged location tails and velocity tiles; for
-    BF16 also the chirp-table Doppler zoom with Mc > 128 (chirp by chirp) and a slab of
-    more than 16 tiles (the generating Doppler zoom)."""
+    """Short contractions (Ms, Mc < 32), ragged location tails and velocity tiles; the
+    chirp-table Doppler zooms with Mc > 128 (chirp by chirp), with right operands cached
+    across several row tiles (FP32: Mc = 8 .. 128), and a slab of more than 16 tiles
+    (the generating Doppler zoom)."""
     say(f"direct shapes ms={ms} mc={mc} n={n} gemm={gemm}")
     s, r, gr = scene_and_radar(1, 9, ms=ms, mc=mc)
     grid = sc.Grid((5.5, -9.0, -12.0, -11.0), (23.0, 9.5, 12.5, 11.0), n)
