@@ -636,17 +636,22 @@ __device__ __forceinline__ void slab_peak(const f32x4 (&dsum)[MAXT], int ntiles,
 // then walks the 16 x 16 tiles of the velocity slab column tile by column
 // tile: the right-operand fragments h[m] Ty[ivy - m] of a column tile are
 // formed once, in registers, for all its row tiles.  |c_q|^2 accumulates per
-// tile in registers across receivers (at most MAXT tiles, MAXS 16-chirp
-// steps).  h of the next receiver is loaded while the current one is in work.
+// tile in registers across receivers (at most MAXT tiles).  STEPS > 0 is the
+// exact number of 16-chirp steps, mcp / 16 (the right operands cached, the
+// loops unrolled without guards); STEPS = 0 forms the right operand step by
+// step (Mc > 128).  h of the next receiver is loaded while the current one is
+// in work.
 // Phases are 64-bit fixed point in cycles; the table values come from the
 // hardware sine and cosine (absolute error near 1e-6, far below the BF16
 // rounding of the operands they feed).
-template <int MAXT, int MAXS, bool STREAM>
+template <int MAXT, int STEPS>
 __global__ __launch_bounds__(kThreads) void direct_doppler_zoom_chirp(Geom g, GridP gp, ToepPlan tp,
                                                                      const uint32_t* __restrict__ hws,
                                                                      float* __restrict__ dec,
                                                                      gh_peak* __restrict__ block,
                                                                      const int64_t* __restrict__ excl, int nexcl) {
+    constexpr bool STREAM = STEPS == 0;
+    constexpr int MAXS = STREAM ? 1 : STEPS;
     extern __shared__ __attribute__((aligned(16))) uint32_t toep_lds[];
     const int lane = threadIdx.x & 63;
     const int r = lane & 15;
@@ -664,7 +669,7 @@ __global__ __launch_bounds__(kThreads) void direct_doppler_zoom_chirp(Geom g, Gr
     const int nvxp = (nvx + 15) & ~15, nvyp = (nvy + 15) & ~15;
     const int tiles_x = nvxp >> 4, ntiles = tiles_x * (nvyp >> 4);
     const int kx = (nvxp > tp.mcp ? nvxp : tp.mcp) - 1, ky = (nvyp > tp.mcp ? nvyp : tp.mcp) - 1;
-    const int steps = tp.mcp >> 4;
+    const int steps = STREAM ? tp.mcp >> 4 : STEPS;
 
     constexpr int kHw = (16 * MAXS + 63) / 64;   // h words per lane held ahead (cached path)
     uint32_t hpre[kHw];
@@ -742,13 +747,11 @@ __global__ __launch_bounds__(kThreads) void direct_doppler_zoom_chirp(Geom g, Gr
                     const uint32_t* pb2 = pb1 + tp.ey;
 #pragma unroll
                     for (int s = 0; s < MAXS; ++s) {
-                        if (s < steps) {
-                            const u32x4 hv = *reinterpret_cast<const u32x4*>(hh + 16 * s + 4 * seg);
+                        const u32x4 hv = *reinterpret_cast<const u32x4*>(hh + 16 * s + 4 * seg);
 #pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                bc[STREAM ? 0 : s][e] = bf16_pair(dot2_bf16(hv[e], pb1[16 * s + e]),
-                                                                  dot2_bf16(hv[e], pb2[16 * s + e]));
-                        }
+                        for (int e = 0; e < 4; ++e)
+                            bc[STREAM ? 0 : s][e] = bf16_pair(dot2_bf16(hv[e], pb1[16 * s + e]),
+                                                              dot2_bf16(hv[e], pb2[16 * s + e]));
                     }
                 }
                 // row ivx = 16 tx + r
@@ -756,7 +759,7 @@ __global__ __launch_bounds__(kThreads) void direct_doppler_zoom_chirp(Geom g, Gr
                 const uint32_t* pa2 = pa1 + tp.ex;
                 f32x4 cr0 = zero4(), ci0 = zero4(), cr1 = zero4(), ci1 = zero4();
                 if constexpr (STREAM) {
-                    // Mc > 16 MAXS: the right operand formed step by step (steps is even)
+                    // Mc > 128: the right operand formed step by step (steps is even)
                     const uint32_t* pb1 = ty1 + 4 * seg - 16 * ty - r + nvyp - 1;
                     const uint32_t* pb2 = pb1 + tp.ey;
                     auto step = [&](int o, f32x4& cr, f32x4& ci) {
@@ -777,15 +780,13 @@ __global__ __launch_bounds__(kThreads) void direct_doppler_zoom_chirp(Geom g, Gr
                 } else {
 #pragma unroll
                     for (int s = 0; s < MAXS; ++s) {
-                        if (s < steps) {
-                            const int o = 16 * s;
-                            const u32x4 ar = {pa1[o], pa1[o + 1], pa1[o + 2], pa1[o + 3]};
-                            const u32x4 ai = {pa2[o], pa2[o + 1], pa2[o + 2], pa2[o + 3]};
-                            f32x4& cr = (s & 1) ? cr1 : cr0;
-                            f32x4& ci = (s & 1) ? ci1 : ci0;
-                            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ar), as_bf16x8(bc[s]), cr, 0, 0, 0);
-                            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ai), as_bf16x8(bc[s]), ci, 0, 0, 0);
-                        }
+                        const int o = 16 * s;
+                        const u32x4 ar = {pa1[o], pa1[o + 1], pa1[o + 2], pa1[o + 3]};
+                        const u32x4 ai = {pa2[o], pa2[o + 1], pa2[o + 2], pa2[o + 3]};
+                        f32x4& cr = (s & 1) ? cr1 : cr0;
+                        f32x4& ci = (s & 1) ? ci1 : ci0;
+                        cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ar), as_bf16x8(bc[s]), cr, 0, 0, 0);
+                        ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ai), as_bf16x8(bc[s]), ci, 0, 0, 0);
                     }
                 }
                 cr0 += cr1;
@@ -1032,12 +1033,18 @@ hipError_t launch_direct(const Geom& g, const GridP& gp, const float2* y, int ge
             const dim3 grid((gp.nloc + cs.waves - 1) / cs.waves), blk(64 * cs.waves);
             const uint32_t* h = static_cast<const uint32_t*>(ws);
 #define GH_CHIRP_LAUNCH(T, S) \
-    hipLaunchKernelGGL((direct_doppler_zoom_chirp<T, 8, S>), grid, blk, lds, st, g, gp, tp, h, dec, block, excl, nexcl)
-            if (cs.maxt == 4) {
-                if (cs.stream) GH_CHIRP_LAUNCH(4, true); else GH_CHIRP_LAUNCH(4, false);
-            } else {
-                if (cs.stream) GH_CHIRP_LAUNCH(16, true); else GH_CHIRP_LAUNCH(16, false);
-            }
+    hipLaunchKernelGGL((direct_doppler_zoom_chirp<T, S>), grid, blk, lds, st, g, gp, tp, h, dec, block, excl, nexcl)
+#define GH_CHIRP_STEPS(T)                                             \
+    do {                                                              \
+        const int steps = tp.mcp >> 4;   /* 1, 2, 4 or 8 unless streamed */ \
+        if (cs.stream) GH_CHIRP_LAUNCH(T, 0);                         \
+        else if (steps == 8) GH_CHIRP_LAUNCH(T, 8);                   \
+        else if (steps == 4) GH_CHIRP_LAUNCH(T, 4);                   \
+        else if (steps == 2) GH_CHIRP_LAUNCH(T, 2);                   \
+        else GH_CHIRP_LAUNCH(T, 1);                                   \
+    } while (0)
+            if (cs.maxt == 4) GH_CHIRP_STEPS(4); else GH_CHIRP_STEPS(16);
+#undef GH_CHIRP_STEPS
 #undef GH_CHIRP_LAUNCH
         } else {
             if ((e = launch_range_bf16<false>(g, gp, y, ws, st)) != hipSuccess) return e;
