@@ -11,7 +11,8 @@
 //                Ex[ivx][m] = exp(-j 2 pi (f0 + ivx fx) m) and Ey[m][ivy] = exp(-j 2 pi ivy fy m);
 //   then |c_q|^2 summed over receivers, the slab write and the block maximum.
 //
-// Matrix-core mapping (64-lane wave, 16 x 16 output tile, FP32 accumulation):
+// Matrix-core mapping of the FP32 range zoom and the generating Doppler zoom
+// (64-lane wave, 16 x 16 output tile, FP32 accumulation):
 //   lane = r + 16 g holds contraction indices k0 + 8 g + e (e = 0..7) of row r
 //   of the left operand and of column r of the right operand.  FP32 issues
 //   eight 16x16x4 products, the e-th taking element e of every lane (any
