@@ -571,6 +571,18 @@ def main():
         flop_dir3 = direct_flop(r3, s3.grid.n)
         del dec3, ws3, y3
 
+        # the step's FP32 direct decision timed on its own, launches back to back (in the step it
+        # runs beside the refinement)
+        for _ in range(3):
+            gh.direct_decision(radar, dgrid, y, ws=ws, dec=ddec, block=dblock, want_argmax=False)
+        ef0, ef1 = ev(), ev()
+        ef0.record(stream)
+        for _ in range(10):
+            gh.direct_decision(radar, dgrid, y, ws=ws, dec=ddec, block=dblock, want_argmax=False)
+        ef1.record(stream)
+        torch.cuda.synchronize()
+        t_dir_f32 = ef0.elapsed_time(ef1) * 1e-3 / 10
+
         # the direct decision with BF16 matrix-core operands, timed on its own (not part of the step)
         ws_b = torch.empty(gh.direct_workspace_bytes(radar, dgrid, gh.GEMM_BF16), dtype=torch.uint8, device=dev)
         ddec_b = torch.empty_like(ddec)
@@ -590,6 +602,7 @@ def main():
             "copy_gbs": copy_gbs,
             "t_gh_sub": t_gh_sub,
             "t_dir_bf16": t_dir_bf16,
+            "t_dir_f32": t_dir_f32,
             "t_dir_bf16_precision": t_dir3,
             "flop_dir_bf16_precision": flop_dir3,
             "err_bf16": err_bf16,
@@ -664,6 +677,12 @@ def main():
                                    "achieved": x["flop_dir_bf16_precision"] / x["t_dir_bf16_precision"] / 1e12,
                                    "frac": x["flop_dir_bf16_precision"] / x["t_dir_bf16_precision"] / 1e12
                                    / BF16_PEAK_TFLOPS}},
+            # the step's FP32 direct decision alone, against the FP32 matrix peak
+            "direct_f32_mfma": {
+                "unit": "TFLOP/s", "peak": FP32_PEAK_TFLOPS, "us": x["t_dir_f32"] * 1e6,
+                "flop": direct_flop(radar, dgrid_s.n),
+                "achieved": direct_flop(radar, dgrid_s.n) / x["t_dir_f32"] / 1e12,
+                "frac": direct_flop(radar, dgrid_s.n) / x["t_dir_f32"] / 1e12 / FP32_PEAK_TFLOPS},
             "speedup_gh_over_direct_same_subgrid": t_dir / x["t_gh_sub"],
             "ms_per_step_p10_p50_p90": x["ms_per_step_p10_p50_p90"],
             "ms_per_step_one_stream": x["ms_per_step_one_stream"],
