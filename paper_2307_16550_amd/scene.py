@@ -106,7 +106,10 @@ class Scene:
         return self.rx.shape[0]
 
 
-CONFIGS = {
+# The seeded single-frame workloads, by number: 1 the small frame the oracle
+# sweeps whole, 2 the paper-scale frame, 3 the precision workload, 5 the
+# differentiation workload (the batching workload is `make_batch`).
+WORKLOADS = {
     1: dict(k=3, ms=64, mc=32, targets=1, snr_db=20.0, n=(32, 32, 8, 8)),
     2: dict(k=4, ms=256, mc=128, targets=3, snr_db=10.0, n=(128, 128, 32, 32)),
     3: dict(k=8, ms=64, mc=32, targets=1, snr_db=20.0, n=(256, 256, 32, 32)),
@@ -163,7 +166,7 @@ def make_scene(cfg: int = 1, trial: int = 0, seed: int | None = None, *, snr_db:
                on_grid: bool = False, targets: int | None = None, k: int | None = None,
                ms: int | None = None, mc: int | None = None, n=None, centered: int = 1) -> Scene:
     """Draw a scene of workload `cfg` (keyword arguments override the recipe)."""
-    spec = dict(CONFIGS[cfg])
+    spec = dict(WORKLOADS[cfg])
     for key, val in (("snr_db", snr_db), ("targets", targets), ("k", k), ("ms", ms), ("mc", mc), ("n", n)):
         if val is not None:
             spec[key] = val
