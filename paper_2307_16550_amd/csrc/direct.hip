@@ -718,20 +718,41 @@ __global__ __launch_bounds__(kThreads) void direct_doppler_zoom_chirp(Geom g, Gr
         }
         const uint64_t hx = bcast64(hxl, q), hy = bcast64(hyl, q);
         // the tables are even in k and the tiles read |k| <= max(nv_pad, mcp) - 1:
-        // one value per |k|, stored at k and -k
-        for (int a = lane; a <= kx; a += 64) {
-            const float2 e = expm_hw(fixed_mul_hi(hx, (uint32_t)(a * a)));   // conj(Tx[+-a])
-            const uint32_t v1 = bf16_pair(e.x, e.y), v2 = bf16_pair(-e.y, e.x);
-            const int n1 = nvxp - 1 - a, n2 = nvxp - 1 + a;
-            if (n1 >= 0) tx1[n1] = v1, tx2[n1] = v2;
-            if (n2 < tp.ex) tx1[n2] = v1, tx2[n2] = v2;
+        // one value per |k|, stored at k and -k.  With Mc <= 32 (at most two steps)
+        // and each table at most 32 values, both are made in one pass of the wave:
+        // lanes 0-31 Tx, lanes 32-63 Ty.
+        bool one_pass = false;
+        if constexpr (!STREAM && MAXS <= 2) {
+            if (kx < 32 && ky < 32) {
+                one_pass = true;
+                const bool isy = lane >= 32;
+                const int a = lane & 31;
+                if (a <= (isy ? ky : kx)) {
+                    const float2 e = expm_hw(fixed_mul_hi(isy ? hy : hx, (uint32_t)(a * a)));   // conj(T[+-a])
+                    const uint32_t v1 = bf16_pair(e.x, e.y), v2 = bf16_pair(-e.y, e.x);
+                    const int c = (isy ? nvyp : nvxp) - 1, len = isy ? tp.ey : tp.ex;
+                    uint32_t* t1 = isy ? ty1 : tx1;
+                    uint32_t* t2 = isy ? ty2 : tx2;
+                    if (c - a >= 0) t1[c - a] = v1, t2[c - a] = v2;
+                    if (c + a < len) t1[c + a] = v1, t2[c + a] = v2;
+                }
+            }
         }
-        for (int a = lane; a <= ky; a += 64) {
-            const float2 e = expm_hw(fixed_mul_hi(hy, (uint32_t)(a * a)));   // conj(Ty[+-a])
-            const uint32_t v1 = bf16_pair(e.x, e.y), v2 = bf16_pair(-e.y, e.x);
-            const int n1 = nvyp - 1 - a, n2 = nvyp - 1 + a;
-            if (n1 >= 0) ty1[n1] = v1, ty2[n1] = v2;
-            if (n2 < tp.ey) ty1[n2] = v1, ty2[n2] = v2;
+        if (!one_pass) {
+            for (int a = lane; a <= kx; a += 64) {
+                const float2 e = expm_hw(fixed_mul_hi(hx, (uint32_t)(a * a)));   // conj(Tx[+-a])
+                const uint32_t v1 = bf16_pair(e.x, e.y), v2 = bf16_pair(-e.y, e.x);
+                const int n1 = nvxp - 1 - a, n2 = nvxp - 1 + a;
+                if (n1 >= 0) tx1[n1] = v1, tx2[n1] = v2;
+                if (n2 < tp.ex) tx1[n2] = v1, tx2[n2] = v2;
+            }
+            for (int a = lane; a <= ky; a += 64) {
+                const float2 e = expm_hw(fixed_mul_hi(hy, (uint32_t)(a * a)));   // conj(Ty[+-a])
+                const uint32_t v1 = bf16_pair(e.x, e.y), v2 = bf16_pair(-e.y, e.x);
+                const int n1 = nvyp - 1 - a, n2 = nvyp - 1 + a;
+                if (n1 >= 0) ty1[n1] = v1, ty2[n1] = v2;
+                if (n2 < tp.ey) ty1[n2] = v1, ty2[n2] = v2;
+            }
         }
         // the tables are private to the wave: its LDS writes only have to land before its reads
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
