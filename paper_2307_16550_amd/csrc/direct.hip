@@ -846,7 +846,8 @@ __global__ __launch_bounds__(kThreads) void direct_doppler_zoom_chirp(Geom g, Gr
 // operands of a column tile are formed once, in registers, for all its row
 // tiles.  STEPS = 0 forms them step by step, eight steps per loop trip
 // (mcp / 2 is a multiple of eight).  h of the next receiver is loaded while the
-// current one is in work.  Table values come from expm_poly.
+// current one is in work (Mc <= 128; larger Mc read h per receiver).  Table
+// values come from expm_poly.
 template <int MAXT, int STEPS>
 __global__ __launch_bounds__(kThreads) void direct_doppler_zoom_chirp_f32(Geom g, GridP gp, ToepPlan tp,
                                                                          const float2* __restrict__ hws,
@@ -854,7 +855,7 @@ __global__ __launch_bounds__(kThreads) void direct_doppler_zoom_chirp_f32(Geom g
                                                                          gh_peak* __restrict__ block,
                                                                          const int64_t* __restrict__ excl, int nexcl) {
     extern __shared__ __attribute__((aligned(16))) float4 toepf_lds[];
-    constexpr int kHw = STEPS > 0 ? (2 * STEPS + 63) / 64 : 1;   // h values per lane held ahead
+    constexpr int kHw = STEPS > 0 ? (2 * STEPS + 63) / 64 : 2;   // h values per lane held ahead
     const int lane = threadIdx.x & 63;
     const int r = lane & 15;
     const int grp = lane >> 4;
@@ -891,7 +892,8 @@ __global__ __launch_bounds__(kThreads) void direct_doppler_zoom_chirp_f32(Geom g
             hpre[u] = m < mc ? hq[m] : make_float2(0.f, 0.f);
         }
     };
-    if (STEPS > 0) load_h(0);
+    const bool pre = STEPS > 0 || tp.mcp <= 64 * kHw;   // else (Mc > 128) h is read per receiver
+    if (pre) load_h(0);
 
     // receiver `lane`: fx / 2 and fy / 2 in 64-bit fixed point
     uint64_t hxl = 0, hyl = 0;
@@ -918,7 +920,7 @@ __global__ __launch_bounds__(kThreads) void direct_doppler_zoom_chirp_f32(Geom g
     for (int q = 0; q < g.k; ++q) {
         // every lane has finished reading receiver q - 1's tables (in-order LDS per wave)
         __builtin_amdgcn_wave_barrier();
-        if constexpr (STEPS > 0) {
+        if (pre) {
 #pragma unroll
             for (int u = 0; u < kHw; ++u) {
                 const int m = lane + 64 * u;
